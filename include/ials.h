@@ -1,0 +1,182 @@
+/*
+ * libials -- iALS++ block-coordinate sweep on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Rendle, Krichene, Zhang, Koren, "iALS++: Speeding up Matrix
+ * Factorization with Subspace Optimization" (arXiv 2110.14044).  Notation:
+ *   S      observations (u, i, y, alpha) (sec. 2), y = alpha = 1 unless given;
+ *   W, H   user (U x d) and item (I x d) embeddings, yhat(u,i) = <w_u, h_i> (eq. 1);
+ *   L      sum_S alpha (yhat - y)^2 + alpha0 sum_{u,i} yhat^2 + lambda (|W|^2 + |H|^2) (eq. 2);
+ *   pi     a block of b consecutive coordinates; the partition is the ascending
+ *          blocks [0,b), [b,2b), ... (the last one shorter when b does not divide d);
+ *   G      Gramian of the fixed side (eq. 4) and its partial form d x |pi| (eq. 7).
+ *
+ * Conventions shared by every call:
+ *   - every call returns ials_status: 0 (IALS_OK) or a negative error code; no
+ *     C++ exception crosses this boundary; ials_last_error() describes the last error;
+ *   - matrices are row-major float32 in device memory unless stated otherwise;
+ *   - W and H are BORROWED: the caller allocates them on the device (U*d and I*d
+ *     floats), keeps them alive until ials_destroy, and the library updates them
+ *     in place;
+ *   - every other buffer the library needs is allocated by ials_create and
+ *     released by ials_destroy; no call in between allocates device memory;
+ *   - work is enqueued asynchronously on the stream given to ials_create; only
+ *     ials_create, ials_loss, ials_foldin, the ials_get_* calls and ials_destroy
+ *     synchronise with it.  A device fault surfaces at the next synchronising
+ *     call as IALS_E_HIP;
+ *   - one context must not be used from two host threads at the same time.
+ */
+#ifndef IALS_H_
+#define IALS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define IALS_API __attribute__((visibility("default")))
+#else
+#define IALS_API
+#endif
+
+typedef enum {
+    IALS_OK = 0,
+    IALS_E_INVALID = -1, /* bad argument: sizes, ids out of range, repeated (u,i), null pointer */
+    IALS_E_NOMEM = -2,   /* device allocation failed or exceeds the configured budget */
+    IALS_E_HIP = -3,     /* a HIP runtime call failed (including an earlier asynchronous fault) */
+    IALS_E_NOT_SPD = -4, /* a block Hessian was not positive definite even in float64 */
+    IALS_E_BUSY = -5,    /* serving: request not admitted now (no free slot or memory); retry */
+    IALS_E_STATE = -6    /* call not valid in the object's current state */
+} ials_status;
+
+typedef enum { IALS_SIDE_USER = 0, IALS_SIDE_ITEM = 1 } ials_side;
+typedef enum { IALS_MAT_W = 0, IALS_MAT_H = 1 } ials_matrix;
+typedef enum { IALS_MEM_HOST = 0, IALS_MEM_DEVICE = 1 } ials_memkind;
+
+/* Arithmetic of the contractions (Gramian, dense term, gathered block Hessians).
+ * FP32: float32 operands on the matrix cores, float32 accumulation.
+ * BF16: bfloat16 operands (round-to-nearest-even from float32) on the matrix
+ *       cores with float32 accumulation; gradients, solves and updates stay float32. */
+typedef enum { IALS_PREC_FP32 = 0, IALS_PREC_BF16 = 1 } ials_precision;
+
+typedef struct {
+    int32_t num_users;          /* U >= 1 */
+    int32_t num_items;          /* I >= 1 */
+    int32_t dim;                /* d >= 1 */
+    int32_t block;              /* b, 1 <= b <= min(d, 64) */
+    float alpha0;               /* weight of the all-pairs term, >= 0 */
+    float lambda;               /* L2 weight, > 0 */
+    int32_t precision;          /* ials_precision */
+    float chol_fallback_ratio;  /* tau: a row whose float32 Cholesky pivots satisfy
+                                   min L_kk^2 < tau * max L_kk^2 (or any pivot <= 0)
+                                   is refactored in float64; <= 0 selects 1e-6 */
+    uint32_t flags;             /* reserved, must be 0 */
+    uint32_t reserved;
+    uint64_t hbm_budget;        /* upper bound on library-owned device bytes; 0 = no bound */
+} ials_config;
+
+typedef struct {
+    int64_t nnz;          /* |S| >= 0 */
+    const int32_t* user;  /* [nnz] user id of each observation, 0 <= u < U */
+    const int32_t* item;  /* [nnz] item id, 0 <= i < I; each (u, i) at most once */
+    const float* y;       /* [nnz] labels, or NULL for all ones */
+    const float* alpha;   /* [nnz] weights > 0, or NULL for all ones */
+    int32_t memkind;      /* ials_memkind of the four arrays above */
+    int32_t reserved;
+} ials_coo;
+
+typedef struct ials_ctx ials_ctx;
+
+typedef struct {
+    int64_t nnz;
+    int32_t num_users, num_items, dim, block, padded_block;
+    int32_t long_rows_user, long_rows_item;  /* rows split into segments */
+    int64_t segments_user, segments_item;
+    int64_t fallback_rows;     /* rows refactored in float64 since create */
+    int64_t passes;            /* block passes run since create */
+    uint64_t device_bytes;     /* library-owned device memory */
+} ials_stats;
+
+/*
+ * Create a training context (sec. 2 problem; Alg. 3 state).  Validates the
+ * configuration and the observations, copies S into library-owned device
+ * memory, builds the user-major and item-major observation indices and
+ * computes yhat from the current W and H.  hip_stream is a hipStream_t (NULL =
+ * the default stream).  On success *out owns every allocation; on failure
+ * nothing is leaked and *out is NULL.  Synchronising.
+ */
+IALS_API ials_status ials_create(const ials_config* cfg, const ials_coo* S, float* W, float* H,
+                        void* hip_stream, ials_ctx** out);
+
+/* Release everything ials_create allocated.  Never frees W or H.  Synchronising. */
+IALS_API ials_status ials_destroy(ials_ctx* ctx);
+
+/*
+ * Partial Gramian (eq. 7) of the current W or H: out = X^T X[:, pi] (d x |pi|,
+ * row-major) for block index `block` (pi = [block*b, min(block*b+b, d))), or the
+ * full Gramian X^T X (d x d, eq. 4) for block = -1.  out is device memory of at
+ * least d*|pi| (or d*d) floats.  Per-chunk float32 partial sums are combined in
+ * float64.  Asynchronous.
+ */
+IALS_API ials_status ials_gramian(ials_ctx* ctx, int32_t which, int32_t block, float* out);
+
+/*
+ * One pass of Alg. 3 for one block and one side: side USER updates w_{u,pi}
+ * for every user against the current H; side ITEM updates h_{i,pi} against the
+ * current W.  Each row gets one Newton step on its block (sec. 4, eq. 8-9:
+ * gradient from the cached yhat and the partial Gramian, Hessian from the
+ * gathered partner sub-vectors), a Cholesky solve, the update and the yhat
+ * patch.  yhat must be current (create, ials_epoch and this call keep it so).
+ * Asynchronous.
+ */
+IALS_API ials_status ials_block_sweep(ials_ctx* ctx, int32_t side, int32_t block);
+
+/*
+ * n_epochs iterations of Alg. 3: recompute yhat (eq. 1), then for every block in
+ * ascending order the user pass followed by the item pass.  Asynchronous.
+ */
+IALS_API ials_status ials_epoch(ials_ctx* ctx, int32_t n_epochs);
+
+/*
+ * Recompute yhat = <w_u, h_i> for every observation from the current W and H
+ * (the first step of an epoch in Alg. 3).  Asynchronous.
+ */
+IALS_API ials_status ials_refresh_predictions(ials_ctx* ctx);
+
+/*
+ * Loss of eq. 2 for the current W and H, with predictions recomputed from W
+ * and H (not the cache) and accumulated in float64; the all-pairs term uses
+ * <W^T W, H^T H>_F with both Gramians formed in float64.  parts (nullable, host,
+ * 3 doubles) receives the observed term, the alpha0 term and the lambda term.
+ * Synchronising; returns IALS_E_INVALID if the result is not finite.
+ */
+IALS_API ials_status ials_loss(ials_ctx* ctx, double* out_host, double* parts_host);
+
+/* Copy the observation index to host buffers (any may be NULL):
+ * side USER: row_ptr[U+1], col[nnz] (item ids); perm ignored.
+ * side ITEM: row_ptr[I+1], col[nnz] (user ids), perm[nnz] = user-major slot of
+ * each item-major slot.  Synchronising. */
+IALS_API ials_status ials_get_csr(ials_ctx* ctx, int32_t side, int64_t* row_ptr, int32_t* col, int32_t* perm);
+
+/* Copy the cached predictions (user-major slot order, nnz floats) to the host. Synchronising. */
+IALS_API ials_status ials_get_predictions(ials_ctx* ctx, float* out_host);
+
+/* Counters and sizes.  Synchronising. */
+IALS_API ials_status ials_get_stats(ials_ctx* ctx, ials_stats* out);
+
+/* Enqueue subsequent work of ctx on another stream (hipStream_t; NULL = default). */
+IALS_API ials_status ials_set_stream(ials_ctx* ctx, void* hip_stream);
+
+/* Text of the last error on ctx (or of the last failed ials_create when ctx is NULL). */
+IALS_API const char* ials_last_error(const ials_ctx* ctx);
+
+/* Library version string. */
+IALS_API const char* ials_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IALS_H_ */

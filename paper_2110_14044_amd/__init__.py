@@ -1,0 +1,79 @@
+"""iALS++ block-coordinate sweep on AMD Instinct MI355X (gfx950).
+
+The work runs in libials.so (hand-written HIP kernels behind a C ABI, declared
+in include/ials.h).  ``binding`` is the ctypes layer with the C names;
+``Trainer`` is a small convenience wrapper that owns W and H as torch device
+tensors.
+"""
+from __future__ import annotations
+
+from . import binding
+from .binding import IalsError
+
+__all__ = ["binding", "IalsError", "Trainer"]
+
+
+class Trainer:
+    """Owns device copies of W, H (torch tensors) and one libials context."""
+
+    def __init__(self, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
+                 stream=None, device: str = "cuda", hbm_budget: int = 0):
+        import numpy as np
+        import torch
+
+        binding.load()
+        self.problem = problem
+        self.W = torch.from_numpy(np.ascontiguousarray(problem.W0)).to(device)
+        self.H = torch.from_numpy(np.ascontiguousarray(problem.H0)).to(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg = binding.make_config(problem.num_users, problem.num_items, problem.dim, problem.block,
+                                  problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget)
+        u = np.ascontiguousarray(problem.user, np.int32)
+        i = np.ascontiguousarray(problem.item, np.int32)
+        y = None if problem.y is None else np.ascontiguousarray(problem.y, np.float32)
+        a = None if problem.alpha is None else np.ascontiguousarray(problem.alpha, np.float32)
+        coo = binding.make_coo(u, i, y, a, binding.IALS_MEM_HOST)
+        self._keep = (u, i, y, a)
+        torch.cuda.synchronize()
+        self.ctx = binding.ials_create(cfg, coo, self.W, self.H, self.stream)
+
+    def epoch(self, n: int = 1):
+        binding.ials_epoch(self.ctx, n)
+
+    def block_sweep(self, side: int, block: int):
+        binding.ials_block_sweep(self.ctx, side, block)
+
+    def refresh_predictions(self):
+        binding.ials_refresh_predictions(self.ctx)
+
+    def loss(self):
+        return binding.ials_loss(self.ctx)
+
+    def gramian(self, which: int, block: int = -1):
+        import torch
+        d, b = self.problem.dim, self.problem.block
+        cols = d if block < 0 else min(b, d - block * b)
+        out = torch.empty((d, cols), dtype=torch.float32, device=self.W.device)
+        binding.ials_gramian(self.ctx, which, block, out)
+        return out
+
+    def predictions(self):
+        return binding.ials_get_predictions(self.ctx, self.problem.nnz)
+
+    def csr(self, side: int):
+        nrows = self.problem.num_users if side == binding.IALS_SIDE_USER else self.problem.num_items
+        return binding.ials_get_csr(self.ctx, side, nrows, self.problem.nnz)
+
+    def stats(self):
+        return binding.ials_get_stats(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            binding.ials_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

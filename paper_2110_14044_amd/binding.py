@@ -1,0 +1,214 @@
+"""ctypes binding of libials (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does
+nothing but convert arguments; all of the work runs in the HIP kernels of
+libials.so.  PyTorch supplies device memory and streams.  If the library has
+not been built, loading fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libials.so")
+
+IALS_OK = 0
+IALS_E_INVALID = -1
+IALS_E_NOMEM = -2
+IALS_E_HIP = -3
+IALS_E_NOT_SPD = -4
+IALS_E_BUSY = -5
+IALS_E_STATE = -6
+
+IALS_SIDE_USER = 0
+IALS_SIDE_ITEM = 1
+IALS_MAT_W = 0
+IALS_MAT_H = 1
+IALS_MEM_HOST = 0
+IALS_MEM_DEVICE = 1
+IALS_PREC_FP32 = 0
+IALS_PREC_BF16 = 1
+
+_STATUS_NAMES = {0: "IALS_OK", -1: "IALS_E_INVALID", -2: "IALS_E_NOMEM", -3: "IALS_E_HIP",
+                 -4: "IALS_E_NOT_SPD", -5: "IALS_E_BUSY", -6: "IALS_E_STATE"}
+
+
+class ials_config(C.Structure):
+    _fields_ = [("num_users", C.c_int32), ("num_items", C.c_int32), ("dim", C.c_int32),
+                ("block", C.c_int32), ("alpha0", C.c_float), ("lambda_", C.c_float),
+                ("precision", C.c_int32), ("chol_fallback_ratio", C.c_float), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32), ("hbm_budget", C.c_uint64)]
+
+
+class ials_coo(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("user", C.c_void_p), ("item", C.c_void_p), ("y", C.c_void_p),
+                ("alpha", C.c_void_p), ("memkind", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ials_stats(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("num_users", C.c_int32), ("num_items", C.c_int32),
+                ("dim", C.c_int32), ("block", C.c_int32), ("padded_block", C.c_int32),
+                ("long_rows_user", C.c_int32), ("long_rows_item", C.c_int32),
+                ("segments_user", C.c_int64), ("segments_item", C.c_int64),
+                ("fallback_rows", C.c_int64), ("passes", C.c_int64), ("device_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IalsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ials_create": (C.c_int, [C.POINTER(ials_config), C.POINTER(ials_coo), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.POINTER(C.c_void_p)]),
+    "ials_destroy": (C.c_int, [C.c_void_p]),
+    "ials_gramian": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "ials_block_sweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "ials_epoch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ials_refresh_predictions": (C.c_int, [C.c_void_p]),
+    "ials_loss": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ials_get_csr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ials_get_predictions": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ials_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ials_stats)]),
+    "ials_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ials_last_error": (C.c_char_p, [C.c_void_p]),
+    "ials_version": (C.c_char_p, []),
+}
+
+
+def load() -> C.CDLL:
+    """Load libials.so (built by paper_2110_14044_amd/build.py).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2110_14044_amd.build` "
+                              "(or __graft_entry__.build()); there is no fallback implementation")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(st: int, ctx=None):
+    if st != IALS_OK:
+        msg = load().ials_last_error(ctx)
+        raise IalsError(st, msg.decode() if msg else "")
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a pointer of {type(x)}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- one function per C entry point ----
+
+def ials_create(cfg: ials_config, S: ials_coo, W, H, stream=None) -> int:
+    out = C.c_void_p()
+    st = load().ials_create(C.byref(cfg), C.byref(S), _ptr(W), _ptr(H), _stream(stream), C.byref(out))
+    _check(st, None)
+    return out.value
+
+
+def ials_destroy(ctx: int) -> None:
+    _check(load().ials_destroy(ctx), None)
+
+
+def ials_gramian(ctx: int, which: int, block: int, out) -> None:
+    _check(load().ials_gramian(ctx, which, block, _ptr(out)), ctx)
+
+
+def ials_block_sweep(ctx: int, side: int, block: int) -> None:
+    _check(load().ials_block_sweep(ctx, side, block), ctx)
+
+
+def ials_epoch(ctx: int, n_epochs: int) -> None:
+    _check(load().ials_epoch(ctx, n_epochs), ctx)
+
+
+def ials_refresh_predictions(ctx: int) -> None:
+    _check(load().ials_refresh_predictions(ctx), ctx)
+
+
+def ials_loss(ctx: int):
+    L = C.c_double()
+    parts = (C.c_double * 3)()
+    _check(load().ials_loss(ctx, C.byref(L), parts), ctx)
+    return L.value, tuple(parts)
+
+
+def ials_get_csr(ctx: int, side: int, nrows: int, nnz: int):
+    ptr = np.zeros(nrows + 1, np.int64)
+    col = np.zeros(max(nnz, 1), np.int32)
+    perm = np.zeros(max(nnz, 1), np.int32) if side == IALS_SIDE_ITEM else None
+    _check(load().ials_get_csr(ctx, side, ptr.ctypes.data, col.ctypes.data,
+                               None if perm is None else perm.ctypes.data), ctx)
+    return ptr, col[:nnz], (None if perm is None else perm[:nnz])
+
+
+def ials_get_predictions(ctx: int, nnz: int) -> np.ndarray:
+    out = np.zeros(max(nnz, 1), np.float32)
+    _check(load().ials_get_predictions(ctx, out.ctypes.data), ctx)
+    return out[:nnz]
+
+
+def ials_get_stats(ctx: int) -> dict:
+    s = ials_stats()
+    _check(load().ials_get_stats(ctx, C.byref(s)), ctx)
+    return s.as_dict()
+
+
+def ials_set_stream(ctx: int, stream) -> None:
+    _check(load().ials_set_stream(ctx, _stream(stream)), ctx)
+
+
+def ials_last_error(ctx: Optional[int] = None) -> str:
+    m = load().ials_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def ials_version() -> str:
+    return load().ials_version().decode()
+
+
+def make_config(num_users, num_items, dim, block, alpha0, lam, precision=IALS_PREC_FP32,
+                chol_fallback_ratio=0.0, hbm_budget=0) -> ials_config:
+    return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, 0, 0,
+                       hbm_budget)
+
+
+def make_coo(user, item, y=None, alpha=None, memkind=IALS_MEM_HOST) -> ials_coo:
+    n = int(user.numel() if hasattr(user, "numel") else user.size)
+    return ials_coo(n, _ptr(user), _ptr(item), _ptr(y), _ptr(alpha), memkind, 0)

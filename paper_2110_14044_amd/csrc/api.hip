@@ -1,0 +1,417 @@
+// C-ABI entry points of libials: context lifecycle and the drivers of Alg. 3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ials_internal.h"
+
+namespace {
+thread_local std::string g_create_error;
+
+void free_ctx(ials_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->owned) (void)hipFree(p);
+    delete c;
+}
+
+struct CreateGuard {
+    ials_ctx* c;
+    bool armed = true;
+    ~CreateGuard() {
+        if (armed && c) free_ctx(c);
+    }
+};
+
+}  // namespace
+
+namespace ials {
+
+hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (c->budget && c->device_bytes + bytes > c->budget) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    c->owned.push_back(*p);
+    c->device_bytes += bytes;
+    return hipSuccess;
+}
+
+}  // namespace ials
+
+namespace {
+
+ials_status fail(ials_ctx* c, ials_status s, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_error = msg;
+    return s;
+}
+
+#define TRY_ALLOC(c, ptr, bytes)                                                           \
+    do {                                                                                   \
+        hipError_t e_ = ials::dev_alloc((c), (void**)&(ptr), (bytes));                     \
+        if (e_ != hipSuccess) {                                                            \
+            g_create_error = std::string("device allocation of ") + std::to_string(bytes) + \
+                             " bytes failed (" + hipGetErrorString(e_) + ")";              \
+            return IALS_E_NOMEM;                                                           \
+        }                                                                                  \
+    } while (0)
+
+#define TRY_HIP_CREATE(expr)                                                               \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            g_create_error = std::string(#expr " failed: ") + hipGetErrorString(e_);      \
+            return IALS_E_HIP;                                                             \
+        }                                                                                  \
+    } while (0)
+
+ials_status check_ctx(ials_ctx* c) {
+    if (!c) {
+        g_create_error = "null context";
+        return IALS_E_INVALID;
+    }
+    return IALS_OK;
+}
+
+int32_t block_width(const ials_ctx* c, int32_t blk) {
+    const int32_t p0 = blk * c->b;
+    return std::min(c->b, c->d - p0);
+}
+
+ials_status run_pass(ials_ctx* c, int side, int32_t blk) {
+    const int32_t p0 = blk * c->b;
+    const int32_t bw = block_width(c, blk);
+    const bool user = side == IALS_SIDE_USER;
+    const float* Xo = user ? c->H : c->W;
+    const int32_t no = user ? c->I : c->U;
+    float* X = user ? c->W : c->H;
+    const int32_t n = user ? c->U : c->I;
+    ials::launch_gramian_slab(c, Xo, no, p0, bw, c->B, c->G, true);
+    ials::launch_dense(c, X, n, p0, bw);
+    ials::launch_sweep(c, side, p0, bw);
+    c->passes += 1;
+    IALS_HIP_TRY(c, hipGetLastError());
+    return IALS_OK;
+}
+
+ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, float* H, void* stream,
+                        ials_ctx** out) {
+    if (!cfg || !S || !W || !H || !out) {
+        g_create_error = "null argument";
+        return IALS_E_INVALID;
+    }
+    *out = nullptr;
+    if (cfg->num_users < 1 || cfg->num_items < 1 || cfg->dim < 1 || cfg->block < 1 || cfg->block > cfg->dim ||
+        cfg->block > 64) {
+        g_create_error = "need num_users >= 1, num_items >= 1, dim >= 1 and 1 <= block <= min(dim, 64)";
+        return IALS_E_INVALID;
+    }
+    if (!(cfg->alpha0 >= 0.f) || !(cfg->lambda > 0.f) || !std::isfinite(cfg->alpha0) || !std::isfinite(cfg->lambda)) {
+        g_create_error = "need alpha0 >= 0 and lambda > 0 (finite)";
+        return IALS_E_INVALID;
+    }
+    if (cfg->precision != IALS_PREC_FP32) {
+        g_create_error = "only IALS_PREC_FP32 is available in this build";
+        return IALS_E_INVALID;
+    }
+    if (cfg->flags != 0) {
+        g_create_error = "flags must be 0";
+        return IALS_E_INVALID;
+    }
+    if (S->nnz < 0 || S->nnz > (int64_t)INT32_MAX || (S->nnz > 0 && (!S->user || !S->item)) ||
+        (S->memkind != IALS_MEM_HOST && S->memkind != IALS_MEM_DEVICE)) {
+        g_create_error = "bad observation set (nnz must be in [0, 2^31), arrays non-null, memkind host or device)";
+        return IALS_E_INVALID;
+    }
+    if ((int64_t)cfg->num_users * cfg->dim > ((int64_t)1 << 40) ||
+        (int64_t)cfg->num_items * cfg->dim > ((int64_t)1 << 40)) {
+        g_create_error = "embedding tables too large";
+        return IALS_E_INVALID;
+    }
+
+    ials_ctx* c = new (std::nothrow) ials_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return IALS_E_NOMEM;
+    }
+    CreateGuard guard{c};
+    c->U = cfg->num_users;
+    c->I = cfg->num_items;
+    c->d = cfg->dim;
+    c->b = cfg->block;
+    c->B = (cfg->block + 15) / 16 * 16;
+    c->alpha0 = cfg->alpha0;
+    c->lambda = cfg->lambda;
+    c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-6f;
+    c->precision = cfg->precision;
+    c->nnz = S->nnz;
+    c->stream = (hipStream_t)stream;
+    c->W = W;
+    c->H = H;
+    c->budget = cfg->hbm_budget;
+    TRY_HIP_CREATE(hipGetDevice(&c->device));
+    int ncu = 0;
+    TRY_HIP_CREATE(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    c->num_cu = std::max(ncu, 1);
+
+    const int64_t nnz = c->nnz;
+    const bool has_y = S->y != nullptr, has_a = S->alpha != nullptr;
+    ials::SideIndex& us = c->side[IALS_SIDE_USER];
+    ials::SideIndex& is = c->side[IALS_SIDE_ITEM];
+    us.nrows = c->U;
+    is.nrows = c->I;
+    TRY_ALLOC(c, c->counters, sizeof(unsigned long long) * ials::CNT_NUM);
+    TRY_ALLOC(c, c->cursors, sizeof(int32_t) * ials::CUR_NUM);
+    TRY_HIP_CREATE(hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * ials::CNT_NUM, c->stream));
+    TRY_HIP_CREATE(hipMemsetAsync(c->cursors, 0, sizeof(int32_t) * ials::CUR_NUM, c->stream));
+    for (int sd = 0; sd < 2; ++sd) {
+        ials::SideIndex& s = c->side[sd];
+        TRY_ALLOC(c, s.ptr, sizeof(int64_t) * (s.nrows + 1));
+        TRY_ALLOC(c, s.col, sizeof(int32_t) * nnz);
+        TRY_ALLOC(c, s.order, sizeof(int32_t) * s.nrows);
+        TRY_ALLOC(c, s.seg_first, sizeof(int32_t) * s.nrows);
+        if (has_y) TRY_ALLOC(c, s.y, sizeof(float) * nnz);
+        if (has_a) TRY_ALLOC(c, s.a, sizeof(float) * nnz);
+    }
+    TRY_ALLOC(c, is.slot, sizeof(int32_t) * nnz);
+    TRY_ALLOC(c, c->yhat, sizeof(float) * nnz);
+
+    // observations on the device (temporary copies when they come from the host)
+    const int32_t *du = S->user, *di = S->item;
+    const float *dy = S->y, *da = S->alpha;
+    std::vector<void*> tmp;
+    struct TmpFree {
+        std::vector<void*>& v;
+        ~TmpFree() {
+            for (void* p : v) (void)hipFree(p);
+        }
+    } tmp_free{tmp};
+    if (S->memkind == IALS_MEM_HOST && nnz > 0) {
+        auto up = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
+            hipError_t e = hipMalloc(dst, bytes);
+            if (e != hipSuccess) return e;
+            tmp.push_back(*dst);
+            return hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+        };
+        void* p;
+        TRY_HIP_CREATE(up(S->user, sizeof(int32_t) * nnz, &p));
+        du = (const int32_t*)p;
+        TRY_HIP_CREATE(up(S->item, sizeof(int32_t) * nnz, &p));
+        di = (const int32_t*)p;
+        if (has_y) {
+            TRY_HIP_CREATE(up(S->y, sizeof(float) * nnz, &p));
+            dy = (const float*)p;
+        }
+        if (has_a) {
+            TRY_HIP_CREATE(up(S->alpha, sizeof(float) * nnz, &p));
+            da = (const float*)p;
+        }
+    }
+    {
+        ials_status st = ials::build_index(c, du, di, dy, da);
+        if (st != IALS_OK) {
+            g_create_error = c->err;
+            return st;
+        }
+    }
+
+    // work buffers of the passes
+    const int64_t nmax = std::max<int64_t>(c->U, c->I);
+    TRY_ALLOC(c, c->G, sizeof(float) * c->d * c->B);
+    TRY_ALLOC(c, c->Dmat, sizeof(float) * c->B * c->B);
+    TRY_ALLOC(c, c->R0, sizeof(float) * nmax * c->B);
+    TRY_ALLOC(c, c->delta, sizeof(float) * nmax * c->B);
+    TRY_ALLOC(c, c->fb_list, sizeof(int32_t) * nmax);
+    size_t gp = 0;
+    for (int32_t n : {c->U, c->I})
+        for (int32_t nc : {c->B, c->d}) gp = std::max(gp, ials::gram_part_floats_needed(n, c->d, nc));
+    c->gram_part_floats = gp;
+    TRY_ALLOC(c, c->gram_part, sizeof(float) * gp);
+    const int64_t nseg = std::max(us.nseg, is.nseg);
+    if (nseg > 0) TRY_ALLOC(c, c->seg_part, sizeof(float) * nseg * ials::seg_part_floats_per_segment(c->B));
+    // loss scratch: one double per user, then float64 Gramian partials (<= 256 MB)
+    const size_t dd = (size_t)c->d * c->d;
+    const size_t chunks = std::max<size_t>(1, std::min<size_t>(64, ((size_t)32 << 20) / dd));
+    c->loss_part_len = (size_t)std::max<int64_t>(c->U, 1) + chunks * dd;
+    TRY_ALLOC(c, c->loss_part, sizeof(double) * c->loss_part_len);
+    TRY_ALLOC(c, c->gram64, sizeof(double) * 2 * dd);
+    TRY_ALLOC(c, c->loss_out, sizeof(double) * 4);
+
+    ials::launch_predict(c);
+    TRY_HIP_CREATE(hipGetLastError());
+    TRY_HIP_CREATE(hipStreamSynchronize(c->stream));
+    guard.armed = false;
+    *out = c;
+    return IALS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ials_status ials_create(const ials_config* cfg, const ials_coo* S, float* W, float* H, void* hip_stream,
+                        ials_ctx** out) {
+    try {
+        g_create_error.clear();
+        return create_impl(cfg, S, W, H, hip_stream, out);
+    } catch (...) {
+        g_create_error = "unexpected host exception in ials_create";
+        return IALS_E_NOMEM;
+    }
+}
+
+ials_status ials_destroy(ials_ctx* ctx) {
+    if (!ctx) return IALS_E_INVALID;
+    free_ctx(ctx);
+    return IALS_OK;
+}
+
+ials_status ials_set_stream(ials_ctx* c, void* hip_stream) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    c->stream = (hipStream_t)hip_stream;
+    return IALS_OK;
+}
+
+ials_status ials_gramian(ials_ctx* c, int32_t which, int32_t block, float* out) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (!out || (which != IALS_MAT_W && which != IALS_MAT_H)) return fail(c, IALS_E_INVALID, "bad gramian arguments");
+    const int32_t nblocks = (c->d + c->b - 1) / c->b;
+    if (block < -1 || block >= nblocks) return fail(c, IALS_E_INVALID, "block index out of range");
+    const float* X = which == IALS_MAT_W ? c->W : c->H;
+    const int32_t n = which == IALS_MAT_W ? c->U : c->I;
+    try {
+        if (block == -1)
+            ials::launch_gramian_slab(c, X, n, 0, c->d, c->d, out, false);
+        else {
+            const int32_t bw = block_width(c, block);
+            ials::launch_gramian_slab(c, X, n, block * c->b, bw, bw, out, false);
+        }
+    } catch (...) {
+        return fail(c, IALS_E_HIP, "launch failed");
+    }
+    IALS_HIP_TRY(c, hipGetLastError());
+    return IALS_OK;
+}
+
+ials_status ials_block_sweep(ials_ctx* c, int32_t side, int32_t block) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    const int32_t nblocks = (c->d + c->b - 1) / c->b;
+    if ((side != IALS_SIDE_USER && side != IALS_SIDE_ITEM) || block < 0 || block >= nblocks)
+        return fail(c, IALS_E_INVALID, "bad side or block index");
+    return run_pass(c, side, block);
+}
+
+ials_status ials_refresh_predictions(ials_ctx* c) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    ials::launch_predict(c);
+    IALS_HIP_TRY(c, hipGetLastError());
+    return IALS_OK;
+}
+
+ials_status ials_epoch(ials_ctx* c, int32_t n_epochs) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (n_epochs < 0) return fail(c, IALS_E_INVALID, "n_epochs < 0");
+    const int32_t nblocks = (c->d + c->b - 1) / c->b;
+    for (int32_t t = 0; t < n_epochs; ++t) {
+        ials::launch_predict(c);
+        for (int32_t blk = 0; blk < nblocks; ++blk) {
+            ials_status s = run_pass(c, IALS_SIDE_USER, blk);
+            if (s != IALS_OK) return s;
+            s = run_pass(c, IALS_SIDE_ITEM, blk);
+            if (s != IALS_OK) return s;
+        }
+    }
+    IALS_HIP_TRY(c, hipGetLastError());
+    return IALS_OK;
+}
+
+ials_status ials_loss(ials_ctx* c, double* out_host, double* parts_host) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (!out_host) return fail(c, IALS_E_INVALID, "null output");
+    ials_status s = ials::launch_loss(c);
+    if (s != IALS_OK) return s;
+    double parts[4] = {0, 0, 0, 0};
+    IALS_HIP_TRY(c, hipMemcpyAsync(parts, c->loss_out, sizeof(double) * 3, hipMemcpyDeviceToHost, c->stream));
+    long long cnt[ials::CNT_NUM];
+    IALS_HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double L = parts[0] + (double)c->alpha0 * parts[1] + (double)c->lambda * parts[2];
+    *out_host = L;
+    if (parts_host) {
+        parts_host[0] = parts[0];
+        parts_host[1] = (double)c->alpha0 * parts[1];
+        parts_host[2] = (double)c->lambda * parts[2];
+    }
+    if (cnt[ials::CNT_NOT_SPD] > 0)
+        return fail(c, IALS_E_NOT_SPD,
+                    std::to_string(cnt[ials::CNT_NOT_SPD]) + " rows had a Hessian that was not SPD in float64");
+    if (!std::isfinite(L)) return fail(c, IALS_E_INVALID, "loss is not finite");
+    return IALS_OK;
+}
+
+ials_status ials_get_csr(ials_ctx* c, int32_t side, int64_t* row_ptr, int32_t* col, int32_t* perm) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (side != IALS_SIDE_USER && side != IALS_SIDE_ITEM) return fail(c, IALS_E_INVALID, "bad side");
+    const ials::SideIndex& s = c->side[side];
+    if (row_ptr)
+        IALS_HIP_TRY(c, hipMemcpyAsync(row_ptr, s.ptr, sizeof(int64_t) * (s.nrows + 1), hipMemcpyDeviceToHost, c->stream));
+    if (col && c->nnz > 0)
+        IALS_HIP_TRY(c, hipMemcpyAsync(col, s.col, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost, c->stream));
+    if (perm && side == IALS_SIDE_ITEM && c->nnz > 0)
+        IALS_HIP_TRY(c, hipMemcpyAsync(perm, s.slot, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost, c->stream));
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return IALS_OK;
+}
+
+ials_status ials_get_predictions(ials_ctx* c, float* out_host) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (!out_host) return fail(c, IALS_E_INVALID, "null output");
+    if (c->nnz > 0)
+        IALS_HIP_TRY(c, hipMemcpyAsync(out_host, c->yhat, sizeof(float) * c->nnz, hipMemcpyDeviceToHost, c->stream));
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return IALS_OK;
+}
+
+ials_status ials_get_stats(ials_ctx* c, ials_stats* o) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (!o) return fail(c, IALS_E_INVALID, "null output");
+    long long cnt[ials::CNT_NUM];
+    IALS_HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memset(o, 0, sizeof(*o));
+    o->nnz = c->nnz;
+    o->num_users = c->U;
+    o->num_items = c->I;
+    o->dim = c->d;
+    o->block = c->b;
+    o->padded_block = c->B;
+    o->long_rows_user = c->side[0].nlong;
+    o->long_rows_item = c->side[1].nlong;
+    o->segments_user = c->side[0].nseg;
+    o->segments_item = c->side[1].nseg;
+    o->fallback_rows = cnt[ials::CNT_FALLBACK_ROWS];
+    o->passes = c->passes;
+    o->device_bytes = c->device_bytes;
+    return IALS_OK;
+}
+
+const char* ials_last_error(const ials_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+const char* ials_version(void) { return "libials 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,387 @@
+// Dense kernels of an iALS++ pass (gfx950, wave64):
+//   k_predict     yhat = <w_u, h_i> for every observation (eq. 1; first step of an epoch, Alg. 3)
+//   k_gram_part   partial Gramian X^T X[:, pi] (eq. 7), split over row chunks, MFMA f32 16x16x4
+//   k_gram_reduce fixed-order float64 sum of the chunk partials
+//   k_make_dmat   alpha0 * G_{pi,pi} + lambda I (the Hessian's dense part, eq. 9)
+//   k_dense       alpha0 * x_r G^{pi} + lambda x_{r,pi} for every row (the gradient's dense part, eq. 8)
+//   loss kernels  eq. 2 in float64: observed term from fresh predictions and
+//                 <W^T W, H^T H>_F with both Gramians formed in float64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ials_internal.h"
+
+namespace ials {
+namespace {
+
+__device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// One wavefront per user; 16 lanes per observation, 4 observations at a time.
+template <bool VEC4>
+__global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ col, const float* __restrict__ W,
+                                                 const float* __restrict__ H, float* __restrict__ yhat) {
+    const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    if (u >= U) return;
+    const float* w = W + (size_t)u * d;
+    const int64_t lo = ptr[u], hi = ptr[u + 1];
+    for (int64_t k0 = lo; k0 < hi; k0 += 4) {
+        const int64_t k = k0 + g4;
+        const bool v = k < hi;
+        const float* h = H + (size_t)(v ? col[k] : 0) * d;
+        float s = 0.f;
+        if (VEC4) {
+            for (int f = 4 * q16; f < d; f += 64) {
+                const float4 a = *reinterpret_cast<const float4*>(w + f);
+                const float4 b = *reinterpret_cast<const float4*>(h + f);
+                s = fmaf(a.x, b.x, s);
+                s = fmaf(a.y, b.y, s);
+                s = fmaf(a.z, b.z, s);
+                s = fmaf(a.w, b.w, s);
+            }
+        } else {
+            for (int f = q16; f < d; f += 16) s = fmaf(w[f], h[f], s);
+        }
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 1);
+        if (v && q16 == 0) yhat[k] = s;
+    }
+}
+
+// Partial Gramian of one row chunk: part[chunk][f][q] = sum_{r in chunk} X[r][f] X[r][p0+q]
+// for f < d, q < ncols (columns q >= bw are zero).  Block = one wavefront owning a
+// 64 x (16*QT) output tile (4 x QT MFMA tiles).
+template <int QT>
+__global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
+                                                  int32_t bw, int32_t ncols, int32_t rows_per_chunk,
+                                                  float* __restrict__ part) {
+    const int lane = threadIdx.x, q16 = lane & 15, g4 = lane >> 4;
+    const int f0 = blockIdx.x * 64, qg0 = blockIdx.y * 16 * QT;
+    const int chunk = blockIdx.z;
+    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+    floatx4 acc[4][QT];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t r = r0; r < r1; r += 4) {
+        const int64_t rr = r + g4;
+        const bool v = rr < r1;
+        const float* xr = X + (size_t)(v ? rr : 0) * d;
+        float a[4], b[QT];
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft) {
+            const int f = f0 + 16 * ft + q16;
+            a[ft] = (v && f < d) ? xr[f] : 0.f;
+        }
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt) {
+            const int q = qg0 + 16 * qt + q16;
+            b[qt] = (v && q < bw) ? xr[p0 + q] : 0.f;
+        }
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt) acc[ft][qt] = mfma4(a[ft], b[qt], acc[ft][qt]);
+    }
+    float* out = part + (size_t)chunk * d * ncols;
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = f0 + 16 * ft + 4 * g4 + j, q = qg0 + 16 * qt + q16;
+                if (f < d && q < ncols) out[(size_t)f * ncols + q] = acc[ft][qt][j];
+            }
+}
+
+__global__ void k_gram_reduce(const float* __restrict__ part, int32_t nchunks, int64_t count, float* __restrict__ out32) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += (double)part[(size_t)c * count + e];
+    out32[e] = (float)s;
+}
+
+// Dmat = alpha0 * G[p0:p0+bw, 0:bw] + lambda I, identity on the padding; also
+// resets the work-queue cursors used by the sweep kernels of this pass.
+__global__ void k_make_dmat(const float* __restrict__ G, int32_t B, int32_t p0, int32_t bw, float alpha0,
+                            float lambda, float* __restrict__ Dmat, int32_t* __restrict__ cursors) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < CUR_NUM) cursors[e] = 0;
+    if (e >= B * B) return;
+    const int p = e / B, q = e % B;
+    float v;
+    if (p < bw && q < bw)
+        v = alpha0 * G[(size_t)(p0 + p) * B + q] + (p == q ? lambda : 0.f);
+    else
+        v = (p == q) ? 1.f : 0.f;
+    Dmat[e] = v;
+}
+
+// R0[r][q] = alpha0 * sum_f X[r][f] G[f][q] + lambda * X[r][p0+q] (0 on padding columns).
+// One wavefront per 64 rows (4 row tiles) x B columns (NT tiles).
+template <int NT>
+__global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, const float* __restrict__ X,
+                                               const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
+                                               float lambda, float* __restrict__ R0) {
+    constexpr int B = 16 * NT;
+    const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int64_t r0 = (int64_t)wave * 64;
+    if (r0 >= n) return;
+    floatx4 acc[4][NT];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int f = 0; f < d; f += 4) {
+        const int ff = f + g4;
+        const bool fv = ff < d;
+        float a[4], b[NT];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const int64_t r = r0 + 16 * rt + q16;
+            a[rt] = (fv && r < n) ? X[(size_t)r * d + ff] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = fv ? G[(size_t)ff * B + 16 * t + q16] : 0.f;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[rt][t] = mfma4(a[rt], b[t], acc[rt][t]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = r0 + 16 * rt + 4 * g4 + j;
+                const int q = 16 * t + q16;
+                if (r < n)
+                    R0[(size_t)r * B + q] =
+                        (q < bw) ? fmaf(alpha0, acc[rt][t][j], lambda * X[(size_t)r * d + p0 + q]) : 0.f;
+            }
+}
+
+// ---- loss (eq. 2) in float64 ----
+
+// Observed term sum_S alpha (<w_u,h_i> - y)^2 with the dot products in float64;
+// one partial per wavefront (user).
+__global__ __launch_bounds__(256) void k_loss_obs(int32_t U, int32_t d, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const float* __restrict__ y,
+                                                  const float* __restrict__ a, const float* __restrict__ W,
+                                                  const float* __restrict__ H, double* __restrict__ part) {
+    const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    if (u >= U) return;
+    const float* w = W + (size_t)u * d;
+    const int64_t lo = ptr[u], hi = ptr[u + 1];
+    double acc = 0.0;
+    for (int64_t k0 = lo; k0 < hi; k0 += 4) {
+        const int64_t k = k0 + g4;
+        const bool v = k < hi;
+        const float* h = H + (size_t)(v ? col[k] : 0) * d;
+        double s = 0.0;
+        for (int f = q16; f < d; f += 16) s = fma((double)w[f], (double)h[f], s);
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 1);
+        if (v && q16 == 0) {
+            const double e = s - (y ? (double)y[k] : 1.0);
+            acc += (a ? (double)a[k] : 1.0) * e * e;
+        }
+    }
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    if (lane == 0) part[u] = acc;
+}
+
+// Float64 Gramian partial: part[chunk][f][g] = sum_{r in chunk} X[r][f] X[r][g];
+// 256 threads own a 64 x 64 output tile (4 x 4 per thread), X staged in LDS.
+__global__ __launch_bounds__(256) void k_gram64_part(int32_t n, int32_t d, const float* __restrict__ X,
+                                                     int32_t rows_per_chunk, double* __restrict__ part) {
+    __shared__ double sf[32][64 + 1];
+    __shared__ double sg[32][64 + 1];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int f0 = blockIdx.x * 64, g0 = blockIdx.y * 64, chunk = blockIdx.z;
+    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+    double acc[4][4] = {};
+    for (int64_t rb = r0; rb < r1; rb += 32) {
+        for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+            const int rr = e / 64, cc = e % 64;
+            const int64_t r = rb + rr;
+            sf[rr][cc] = (r < r1 && f0 + cc < d) ? (double)X[(size_t)r * d + f0 + cc] : 0.0;
+            sg[rr][cc] = (r < r1 && g0 + cc < d) ? (double)X[(size_t)r * d + g0 + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < 32; ++rr) {
+            double xf[4], xg[4];
+            for (int i = 0; i < 4; ++i) xf[i] = sf[rr][ty + 16 * i];
+            for (int j = 0; j < 4; ++j) xg[j] = sg[rr][tx + 16 * j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(xf[i], xg[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    double* out = part + (size_t)chunk * d * d;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const int f = f0 + ty + 16 * i, g = g0 + tx + 16 * j;
+            if (f < d && g < d) out[(size_t)f * d + g] = acc[i][j];
+        }
+}
+
+__global__ void k_gram64_reduce(const double* __restrict__ part, int32_t nchunks, int64_t count,
+                                double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * count + e];
+    out[e] = s;
+}
+
+// out[0] = observed term, out[1] = <GW, GH>_F, out[2] = tr GW + tr GH (one block, fixed order).
+__global__ __launch_bounds__(256) void k_loss_combine(const double* __restrict__ obs_part, int64_t nobs,
+                                                      const double* __restrict__ GW, const double* __restrict__ GH,
+                                                      int32_t d, double* __restrict__ out) {
+    __shared__ double red[3][256];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t e = threadIdx.x; e < nobs; e += 256) s0 += obs_part[e];
+    const int64_t dd = (int64_t)d * d;
+    for (int64_t e = threadIdx.x; e < dd; e += 256) s1 += GW[e] * GH[e];
+    for (int64_t f = threadIdx.x; f < d; f += 256) s2 += GW[f * d + f] + GH[f * d + f];
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+int chunk_rows_for(int64_t n, int64_t tiles, int64_t target_blocks, int64_t min_rows) {
+    int64_t chunks = std::max<int64_t>(1, target_blocks / std::max<int64_t>(tiles, 1));
+    int64_t rows = (n + chunks - 1) / chunks;
+    rows = std::max<int64_t>(rows, min_rows);
+    rows = (rows + 3) / 4 * 4;
+    return (int)std::max<int64_t>(rows, 4);
+}
+
+}  // namespace
+
+size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols) {
+    const int64_t tiles = (int64_t)((d + 63) / 64) * ((ncols + 63) / 64);
+    const int rows = chunk_rows_for(n, tiles, 2048, 64);
+    const int64_t chunks = (n + rows - 1) / rows;
+    return (size_t)std::max<int64_t>(chunks, 1) * d * ncols;
+}
+
+void launch_predict(ials_ctx* c) {
+    const SideIndex& us = c->side[IALS_SIDE_USER];
+    if (c->U == 0 || c->nnz == 0) return;
+    if (c->d % 64 == 0)
+        hipLaunchKernelGGL(k_predict<true>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col,
+                           c->W, c->H, c->yhat);
+    else
+        hipLaunchKernelGGL(k_predict<false>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, c->d, us.ptr,
+                           us.col, c->W, c->H, c->yhat);
+}
+
+// out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw); with make_dmat
+// also forms Dmat for the pass and resets the sweep cursors.
+void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols, float* out,
+                         bool make_dmat) {
+    const int32_t d = c->d;
+    const int64_t ft = (d + 63) / 64;
+    const int qt16 = (ncols + 15) / 16;
+    const int QT = qt16 >= 4 ? 4 : (qt16 >= 2 ? 2 : 1);
+    const int64_t qg = (ncols + 16 * QT - 1) / (16 * QT);
+    const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
+    const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
+    dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
+    if (QT == 4)
+        hipLaunchKernelGGL(k_gram_part<4>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+    else if (QT == 2)
+        hipLaunchKernelGGL(k_gram_part<2>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+    else
+        hipLaunchKernelGGL(k_gram_part<1>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+    const int64_t count = (int64_t)d * ncols;
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 256)), dim3(256), 0, c->stream, c->gram_part, (int32_t)chunks,
+                       count, out);
+    if (make_dmat)
+        hipLaunchKernelGGL(k_make_dmat, dim3(nblk(std::max(c->B * c->B, (int)CUR_NUM), 256)), dim3(256), 0, c->stream,
+                           out, c->B, p0, bw, c->alpha0, c->lambda, c->Dmat, c->cursors);
+}
+
+void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw) {
+    if (n == 0) return;
+    const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
+    switch (c->B) {
+        case 16:
+            hipLaunchKernelGGL(k_dense<1>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
+                               c->lambda, c->R0);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_dense<2>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
+                               c->lambda, c->R0);
+            break;
+        case 48:
+            hipLaunchKernelGGL(k_dense<3>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
+                               c->lambda, c->R0);
+            break;
+        default:
+            hipLaunchKernelGGL(k_dense<4>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
+                               c->lambda, c->R0);
+            break;
+    }
+}
+
+ials_status launch_loss(ials_ctx* c) {
+    hipStream_t st = c->stream;
+    const int32_t d = c->d;
+    const SideIndex& us = c->side[IALS_SIDE_USER];
+    if (c->U > 0)
+        hipLaunchKernelGGL(k_loss_obs, dim3(nblk(c->U, 4)), dim3(256), 0, st, c->U, d, us.ptr, us.col, us.y, us.a, c->W,
+                           c->H, c->loss_part);
+    // float64 Gramians; partials reuse the loss scratch after the observed partials
+    double* part = c->loss_part + std::max<int64_t>(c->U, 1);
+    const size_t part_cap = c->loss_part_len - (size_t)std::max<int64_t>(c->U, 1);
+    const int64_t tiles = (int64_t)((d + 63) / 64) * ((d + 63) / 64);
+    for (int m = 0; m < 2; ++m) {
+        const float* X = m == 0 ? c->W : c->H;
+        const int64_t n = m == 0 ? c->U : c->I;
+        const int64_t max_chunks = std::max<int64_t>(1, (int64_t)(part_cap / ((size_t)d * d)));
+        int64_t chunks = std::min<int64_t>(max_chunks, std::max<int64_t>(1, 2048 / tiles));
+        int64_t rows = (n + chunks - 1) / chunks;
+        rows = std::max<int64_t>(rows, 32);
+        chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
+        dim3 grid((unsigned)((d + 63) / 64), (unsigned)((d + 63) / 64), (unsigned)chunks);
+        hipLaunchKernelGGL(k_gram64_part, grid, dim3(256), 0, st, (int32_t)n, d, X, (int32_t)rows, part);
+        const int64_t count = (int64_t)d * d;
+        hipLaunchKernelGGL(k_gram64_reduce, dim3(nblk(count, 256)), dim3(256), 0, st, part, (int32_t)chunks, count,
+                           c->gram64 + (size_t)m * count);
+    }
+    hipLaunchKernelGGL(k_loss_combine, dim3(1), dim3(256), 0, st, c->loss_part, (int64_t)c->U, c->gram64,
+                       c->gram64 + (size_t)d * d, d, c->loss_out);
+    IALS_HIP_TRY(c, hipGetLastError());
+    return IALS_OK;
+}
+
+}  // namespace ials

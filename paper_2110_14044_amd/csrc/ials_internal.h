@@ -1,0 +1,117 @@
+// Internal declarations of libials (gfx950).  Not part of the public boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ials.h"
+
+namespace ials {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+// Rows longer than this many observations are split into segments of kSegLen,
+// each accumulated by its own wavefront, then reduced in a fixed order.
+constexpr int kSegLen = 1024;
+
+// Device-side counters/flags block (int64), zeroed at create.
+enum Counter : int {
+    CNT_FALLBACK_ROWS = 0,  // rows refactored in float64
+    CNT_NOT_SPD = 1,        // rows not SPD even in float64
+    CNT_BAD_INPUT = 2,      // create-time validation failures
+    CNT_DUPLICATE = 3,      // repeated (u, i) pairs
+    CNT_NUM = 8
+};
+
+// Work-queue cursors (int32), reset by the Gramian reduction kernel of each pass.
+enum Cursor : int { CUR_ROWS = 0, CUR_SEGS = 1, CUR_PATCH = 2, CUR_FALLBACK = 3, CUR_FB_LIST = 4, CUR_NUM = 8 };
+
+struct SideIndex {
+    int32_t nrows = 0;
+    int64_t* ptr = nullptr;       // [nrows+1]
+    int32_t* col = nullptr;       // [nnz] partner ids
+    int32_t* slot = nullptr;      // [nnz] yhat position (item side only; null = identity)
+    float* y = nullptr;           // [nnz] labels in this side's order (null = ones)
+    float* a = nullptr;           // [nnz] weights in this side's order (null = ones)
+    int32_t* order = nullptr;     // [nrows] rows by decreasing length
+    int32_t* seg_first = nullptr; // [nrows] first segment of a long row, -1 otherwise
+    int32_t* seg_row = nullptr;   // [nseg]
+    int64_t* seg_lo = nullptr;    // [nseg]
+    int64_t* seg_hi = nullptr;    // [nseg]
+    int32_t nseg = 0;
+    int32_t nlong = 0;
+    int64_t max_len = 0;
+};
+
+}  // namespace ials
+
+struct ials_ctx {
+    // configuration
+    int32_t U = 0, I = 0, d = 0, b = 0, B = 0;  // B = b padded to a multiple of 16
+    float alpha0 = 0.f, lambda = 0.f, tau = 1e-6f;
+    int32_t precision = 0;
+    int64_t nnz = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 256;
+
+    // borrowed
+    float* W = nullptr;
+    float* H = nullptr;
+
+    // owned
+    ials::SideIndex side[2];
+    float* yhat = nullptr;       // [nnz] user-major order
+    float* G = nullptr;          // [d * B] partial Gramian of the fixed side
+    float* Dmat = nullptr;       // [B * B] alpha0 * G_pipi + lambda I (identity on padding)
+    float* R0 = nullptr;         // [max(U,I) * B] dense gradient term
+    float* gram_part = nullptr;  // split-K partials
+    size_t gram_part_floats = 0;
+    float* seg_part = nullptr;   // per-segment partial Hessian + gradient
+    float* delta = nullptr;      // [max(U,I) * B]
+    int32_t* fb_list = nullptr;  // [max(U,I)]
+    int32_t* cursors = nullptr;  // [CUR_NUM]
+    unsigned long long* counters = nullptr;  // [CNT_NUM]
+    double* loss_part = nullptr;  // loss partial sums
+    size_t loss_part_len = 0;
+    double* gram64 = nullptr;    // [2 * d * d] float64 Gramians for the loss
+    double* loss_out = nullptr;  // [4]
+    uint64_t device_bytes = 0;
+    uint64_t budget = 0;
+    int64_t passes = 0;
+
+    std::string err;
+    std::vector<void*> owned;  // every device allocation of this context
+};
+
+namespace ials {
+
+// Host-side launchers (implemented in the .hip files).
+ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_item, const float* d_y,
+                        const float* d_a);
+void launch_predict(ials_ctx* c);
+void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols,
+                         float* out, bool make_dmat);
+void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw);
+void launch_sweep(ials_ctx* c, int side, int32_t p0, int32_t bw);
+ials_status launch_loss(ials_ctx* c);
+size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
+size_t seg_part_floats_per_segment(int32_t B);
+
+// Allocation helper that tracks the context's byte count and budget.
+hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes);
+
+}  // namespace ials
+
+#define IALS_HIP_TRY(c, expr)                                                          \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (c)->err = std::string(#expr " failed: ") + hipGetErrorString(e_);         \
+            return IALS_E_HIP;                                                         \
+        }                                                                              \
+    } while (0)

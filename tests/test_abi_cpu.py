@@ -1,0 +1,69 @@
+"""The C-ABI library loads on a CPU-only host and exports every symbol include/ials.h declares.
+
+No compute call is made here; only argument validation that returns before
+any device work.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2110_14044_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"IALS_API\s+[\w\s\*]+?\b(ials_\w+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libials.so is not built (run __graft_entry__.build())")
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(binding.exported_symbols()) | set(names)
+    assert set(binding.exported_symbols()) == set(names)
+
+
+def test_version_string(lib):
+    assert "gfx950" in binding.ials_version()
+
+
+def test_create_rejects_bad_config_before_device_work(lib):
+    S = binding.ials_coo(0, None, None, None, None, 0, 0)
+    for cfg in [binding.make_config(0, 10, 16, 8, 0.1, 0.1), binding.make_config(10, 10, 16, 0, 0.1, 0.1),
+                binding.make_config(10, 10, 16, 32, 0.1, 0.1), binding.make_config(10, 10, 16, 8, 0.1, 0.0),
+                binding.make_config(10, 10, 128, 65, 0.1, 0.1), binding.make_config(10, 10, 16, 8, -1.0, 0.1)]:
+        out = C.c_void_p()
+        st = lib.ials_create(C.byref(cfg), C.byref(S), 1, 1, None, C.byref(out))
+        assert st == binding.IALS_E_INVALID
+        assert out.value is None
+        assert binding.ials_last_error(None)
+    out = C.c_void_p()
+    cfg = binding.make_config(10, 10, 16, 8, 0.1, 0.1)
+    assert lib.ials_create(None, C.byref(S), 1, 1, None, C.byref(out)) == binding.IALS_E_INVALID
+    assert lib.ials_create(C.byref(cfg), C.byref(S), None, 1, None, C.byref(out)) == binding.IALS_E_INVALID
+    bad = binding.ials_coo(-1, None, None, None, None, 0, 0)
+    assert lib.ials_create(C.byref(cfg), C.byref(bad), 1, 1, None, C.byref(out)) == binding.IALS_E_INVALID
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.ials_epoch(None, 1) == binding.IALS_E_INVALID
+    assert lib.ials_block_sweep(None, 0, 0) == binding.IALS_E_INVALID
+    assert lib.ials_destroy(None) == binding.IALS_E_INVALID
+    L = C.c_double()
+    assert lib.ials_loss(None, C.byref(L), None) == binding.IALS_E_INVALID

@@ -1,0 +1,151 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Tolerances: index arrays bit-exact; float32 embeddings within 1e-4 relative
+(Frobenius) and the loss within 1e-6 relative of the float64 oracle after one
+epoch from the identical start; single kernels (predictions, Gramians, one
+pass) within the float32 rounding of their own arithmetic.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import gpu_trainer, host, need_gpu, oracle_setup, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def test_csr_and_perm_bit_exact():
+    p = synth.make_problem("tiny")
+    say("csr tiny")
+    tr = gpu_trainer(p)
+    csr, _, _ = oracle_setup(p)
+    uptr, ucol, _ = tr.csr(0)
+    iptr, icol, perm = tr.csr(1)
+    assert np.array_equal(uptr, csr.uptr) and np.array_equal(ucol, csr.ucol)
+    assert np.array_equal(iptr, csr.iptr) and np.array_equal(icol, csr.icol)
+    assert np.array_equal(perm, csr.perm)
+    tr.close()
+
+
+def test_predictions_gramian_and_loss_at_start():
+    p = synth.make_problem("tiny")
+    tr = gpu_trainer(p)
+    csr, _, _ = oracle_setup(p)
+    yh = tr.predictions()
+    ref = oracle.predict(csr, p.W0, p.H0)
+    assert rel(yh, ref) < 1e-6
+    for which, X in ((0, p.W0), (1, p.H0)):
+        G = host(tr.gramian(which, -1))
+        assert rel(G, oracle.gramian(X)) < 1e-5
+        for blk in range(p.dim // p.block):
+            Gb = host(tr.gramian(which, blk))
+            assert rel(Gb, oracle.gramian(X, blk * p.block, p.block)) < 1e-5
+    L, parts = tr.loss()
+    Lr = oracle.loss(csr, p.W0, p.H0, p.alpha0, p.lam)
+    assert abs(L - Lr) <= 1e-10 * abs(Lr), (L, Lr)
+    tr.close()
+
+
+def _one_pass_check(p, side, blk, tol):
+    tr = gpu_trainer(p)
+    csr, ys, as_ = oracle_setup(p)
+    W = p.W0.astype(np.float64).copy()
+    H = p.H0.astype(np.float64).copy()
+    yhat = oracle.predict(csr, W, H)
+    b = p.block
+    p0, bw = blk * b, min(b, p.dim - blk * b)
+    if side == 1:  # item pass from the start state
+        pass
+    G = oracle.gramian(H if side == 0 else W, p0, bw)
+    oracle.block_pass(csr, "user" if side == 0 else "item", p0, bw, p.alpha0, p.lam, W, H, yhat, G, ys, as_)
+    tr.block_sweep(side, blk)
+    Wg, Hg = host(tr.W), host(tr.H)
+    assert rel(Wg, W) < tol and rel(Hg, H) < tol, (rel(Wg, W), rel(Hg, H))
+    assert rel(tr.predictions(), yhat) < tol
+    tr.close()
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_one_pass_tiny(side):
+    p = synth.make_problem("tiny")
+    _one_pass_check(p, side, 1, 1e-5)
+
+
+def _epoch_check(p, epochs, tol_w, tol_l, **kw):
+    tr = gpu_trainer(p, **kw)
+    csr, ys, as_ = oracle_setup(p)
+    W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, epochs, ys, as_)
+    tr.epoch(epochs)
+    L, _ = tr.loss()
+    Wg, Hg = host(tr.W), host(tr.H)
+    ew, eh, el = rel(Wg, W), rel(Hg, H), abs(L - losses[-1]) / abs(losses[-1])
+    say(f"{p.name} d={p.dim} b={p.block} epochs={epochs}: W {ew:.2e} H {eh:.2e} loss {el:.2e}")
+    assert ew < tol_w and eh < tol_w and el < tol_l
+    st = tr.stats()
+    tr.close()
+    return st
+
+
+def test_tiny_one_epoch_meets_fp32_bar():
+    _epoch_check(synth.make_problem("tiny"), 1, 1e-4, 1e-6)
+
+
+def test_tiny_four_epochs():
+    _epoch_check(synth.make_problem("tiny"), 4, 1e-3, 1e-5)
+
+
+def test_labels_weights_and_empty_rows():
+    p = synth.small_problem(31, 300, 200, 2500, 32, 16, labels=True, alpha0=0.2, lam=0.05)
+    _epoch_check(p, 2, 1e-4, 1e-6)
+    p = synth.small_problem(32, 400, 300, 250, 16, 8, labels=True)  # most rows empty
+    _epoch_check(p, 2, 1e-4, 1e-6)
+
+
+@pytest.mark.parametrize("d,b", [(20, 8), (48, 48), (64, 64), (16, 1), (40, 16), (128, 64)])
+def test_block_shapes(d, b):
+    p = synth.small_problem(40 + d + b, 500, 300, 6000, d, b, labels=False, std=0.1)
+    _epoch_check(p, 1, 1e-4, 1e-6)
+
+
+def test_long_rows_split_into_segments():
+    # 120 items x 3000 users with 60k observations: most item rows exceed one segment
+    p = synth.small_problem(50, 3000, 120, 60_000, 32, 32, labels=True, zipf_s=0.8, std=0.1)
+    st = _epoch_check(p, 1, 1e-4, 1e-6)
+    assert st["segments_item"] > 0 and st["long_rows_item"] > 0
+
+
+def test_forced_float64_fallback_matches():
+    p = synth.make_problem("tiny")
+    st = _epoch_check(p, 1, 1e-4, 1e-6, chol_fallback_ratio=1.0)
+    assert st["fallback_rows"] == (p.num_users + p.num_items) * (p.dim // p.block)
+
+
+def test_bitwise_deterministic():
+    p = synth.small_problem(60, 2000, 100, 40_000, 64, 32, zipf_s=0.9, std=0.1)
+    outs = []
+    for _ in range(2):
+        tr = gpu_trainer(p)
+        tr.epoch(2)
+        outs.append((host(tr.W), host(tr.H), tr.predictions()))
+        tr.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_invalid_observations_rejected():
+    from paper_2110_14044_amd import IalsError
+    p = synth.small_problem(70, 50, 40, 200, 16, 8)
+    p.item[3] = p.item[4]
+    p.user[3] = p.user[4]  # duplicate pair
+    with pytest.raises(IalsError, match="IALS_E_INVALID"):
+        gpu_trainer(p)
+    p = synth.small_problem(71, 50, 40, 200, 16, 8)
+    p.item[0] = 40  # out of range
+    with pytest.raises(IalsError, match="IALS_E_INVALID"):
+        gpu_trainer(p)
