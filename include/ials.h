@@ -166,6 +166,36 @@ IALS_API ials_status ials_get_predictions(ials_ctx* ctx, float* out_host);
 /* Counters and sizes.  Synchronising. */
 IALS_API ials_status ials_get_stats(ials_ctx* ctx, ials_stats* out);
 
+/* Kernel families timed by the profiling hooks below (index into the arrays). */
+typedef enum {
+    IALS_K_PREDICT = 0,       /* yhat recompute at the start of an epoch (eq. 1) */
+    IALS_K_GRAM_USER = 1,     /* partial Gramian of H for a user pass (eq. 7) */
+    IALS_K_GRAM_ITEM = 2,     /* partial Gramian of W for an item pass */
+    IALS_K_DENSE_USER = 3,    /* alpha0 w_u G^pi + lambda w_{u,pi} for every user (eq. 8) */
+    IALS_K_DENSE_ITEM = 4,
+    IALS_K_SEG_USER = 5,      /* partial Hessians/gradients of long-row segments */
+    IALS_K_SEG_ITEM = 6,
+    IALS_K_ROWS_USER = 7,     /* gather + Hessian + Cholesky + update + yhat patch per row */
+    IALS_K_ROWS_ITEM = 8,
+    IALS_K_FALLBACK_USER = 9, /* float64 redo of rejected factorisations */
+    IALS_K_FALLBACK_ITEM = 10,
+    IALS_K_PATCH_USER = 11,   /* yhat patch of long-row segments */
+    IALS_K_PATCH_ITEM = 12,
+    IALS_K_LOSS = 13,
+    IALS_K_NUM = 16
+} ials_kernel;
+
+/* Turn per-kernel timing on (1) or off (0).  While on, every launch of the
+ * families above is bracketed by HIP events recorded on the context's stream
+ * (event objects are created here, not device memory).  Turning it on clears
+ * the accumulated times. */
+IALS_API ials_status ials_profile_enable(ials_ctx* ctx, int32_t enable);
+
+/* Accumulated time (ms, host array of IALS_K_NUM) and launch count per family
+ * since profiling was enabled or last read; resets the accumulators.
+ * Synchronising. */
+IALS_API ials_status ials_profile_read(ials_ctx* ctx, double* total_ms, int64_t* launches);
+
 /* Enqueue subsequent work of ctx on another stream (hipStream_t; NULL = default). */
 IALS_API ials_status ials_set_stream(ials_ctx* ctx, void* hip_stream);
 

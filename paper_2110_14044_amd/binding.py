@@ -82,6 +82,8 @@ _SIGS = {
     "ials_get_predictions": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ials_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ials_stats)]),
     "ials_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ials_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ials_profile_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ials_last_error": (C.c_char_p, [C.c_void_p]),
     "ials_version": (C.c_char_p, []),
 }
@@ -192,6 +194,22 @@ def ials_get_stats(ctx: int) -> dict:
 
 def ials_set_stream(ctx: int, stream) -> None:
     _check(load().ials_set_stream(ctx, _stream(stream)), ctx)
+
+
+KERNEL_NAMES = ["predict", "gram_user", "gram_item", "dense_user", "dense_item", "seg_user", "seg_item",
+                "rows_user", "rows_item", "fallback_user", "fallback_item", "patch_user", "patch_item", "loss",
+                "k14", "k15"]
+
+
+def ials_profile_enable(ctx: int, enable: bool) -> None:
+    _check(load().ials_profile_enable(ctx, 1 if enable else 0), ctx)
+
+
+def ials_profile_read(ctx: int) -> dict:
+    ms = np.zeros(16, np.float64)
+    cnt = np.zeros(16, np.int64)
+    _check(load().ials_profile_read(ctx, ms.ctypes.data, cnt.ctypes.data), ctx)
+    return {KERNEL_NAMES[k]: (float(ms[k]), int(cnt[k])) for k in range(16) if cnt[k] > 0}
 
 
 def ials_last_error(ctx: Optional[int] = None) -> str:

@@ -17,6 +17,7 @@ void free_ctx(ials_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     for (void* p : c->owned) (void)hipFree(p);
+    for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -98,8 +99,14 @@ ials_status run_pass(ials_ctx* c, int side, int32_t blk) {
     const int32_t no = user ? c->I : c->U;
     float* X = user ? c->W : c->H;
     const int32_t n = user ? c->U : c->I;
-    ials::launch_gramian_slab(c, Xo, no, p0, bw, c->B, c->G, true);
-    ials::launch_dense(c, X, n, p0, bw);
+    {
+        ials::ProfScope ps(c, IALS_K_GRAM_USER + side);
+        ials::launch_gramian_slab(c, Xo, no, p0, bw, c->B, c->G, true);
+    }
+    {
+        ials::ProfScope ps(c, IALS_K_DENSE_USER + side);
+        ials::launch_dense(c, X, n, p0, bw);
+    }
     ials::launch_sweep(c, side, p0, bw);
     c->passes += 1;
     IALS_HIP_TRY(c, hipGetLastError());
@@ -231,6 +238,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     const int64_t nmax = std::max<int64_t>(c->U, c->I);
     TRY_ALLOC(c, c->G, sizeof(float) * c->d * c->B);
     TRY_ALLOC(c, c->Dmat, sizeof(float) * c->B * c->B);
+    TRY_ALLOC(c, c->dtiles, sizeof(float) * 256 * (c->B / 16) * (c->B / 16 + 1) / 2);
     TRY_ALLOC(c, c->R0, sizeof(float) * nmax * c->B);
     TRY_ALLOC(c, c->delta, sizeof(float) * nmax * c->B);
     TRY_ALLOC(c, c->fb_list, sizeof(int32_t) * nmax);
@@ -325,7 +333,10 @@ ials_status ials_epoch(ials_ctx* c, int32_t n_epochs) {
     if (n_epochs < 0) return fail(c, IALS_E_INVALID, "n_epochs < 0");
     const int32_t nblocks = (c->d + c->b - 1) / c->b;
     for (int32_t t = 0; t < n_epochs; ++t) {
-        ials::launch_predict(c);
+        {
+            ials::ProfScope ps(c, IALS_K_PREDICT);
+            ials::launch_predict(c);
+        }
         for (int32_t blk = 0; blk < nblocks; ++blk) {
             ials_status s = run_pass(c, IALS_SIDE_USER, blk);
             if (s != IALS_OK) return s;
@@ -340,7 +351,11 @@ ials_status ials_epoch(ials_ctx* c, int32_t n_epochs) {
 ials_status ials_loss(ials_ctx* c, double* out_host, double* parts_host) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
     if (!out_host) return fail(c, IALS_E_INVALID, "null output");
-    ials_status s = ials::launch_loss(c);
+    ials_status s;
+    {
+        ials::ProfScope ps(c, IALS_K_LOSS);
+        s = ials::launch_loss(c);
+    }
     if (s != IALS_OK) return s;
     double parts[4] = {0, 0, 0, 0};
     IALS_HIP_TRY(c, hipMemcpyAsync(parts, c->loss_out, sizeof(double) * 3, hipMemcpyDeviceToHost, c->stream));
@@ -404,6 +419,43 @@ ials_status ials_get_stats(ials_ctx* c, ials_stats* o) {
     o->fallback_rows = cnt[ials::CNT_FALLBACK_ROWS];
     o->passes = c->passes;
     o->device_bytes = c->device_bytes;
+    return IALS_OK;
+}
+
+ials_status ials_profile_enable(ials_ctx* c, int32_t enable) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (enable && c->prof_pool.empty()) {
+        constexpr size_t kPairs = 16384;
+        c->prof_pool.resize(2 * kPairs, nullptr);
+        c->prof_kind.resize(kPairs, 0);
+        for (auto& e : c->prof_pool) IALS_HIP_TRY(c, hipEventCreate(&e));
+    }
+    c->prof = enable != 0;
+    c->prof_used = 0;
+    for (int k = 0; k < IALS_K_NUM; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_count[k] = 0;
+    }
+    return IALS_OK;
+}
+
+ials_status ials_profile_read(ials_ctx* c, double* total_ms, int64_t* launches) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->prof_used; ++i) {
+        float ms = 0.f;
+        IALS_HIP_TRY(c, hipEventElapsedTime(&ms, c->prof_pool[2 * i], c->prof_pool[2 * i + 1]));
+        c->prof_ms[c->prof_kind[i]] += ms;
+        c->prof_count[c->prof_kind[i]] += 1;
+    }
+    c->prof_used = 0;
+    for (int k = 0; k < IALS_K_NUM; ++k) {
+        if (total_ms) total_ms[k] = c->prof_ms[k];
+        if (launches) launches[k] = c->prof_count[k];
+        c->prof_ms[k] = 0.0;
+        c->prof_count[k] = 0;
+    }
     return IALS_OK;
 }
 

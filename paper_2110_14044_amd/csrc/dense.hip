@@ -56,6 +56,60 @@ __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int
     }
 }
 
+// Same computation for d = 64*J with the row held in registers: the partner
+// ids of 64 observations are loaded at once and 4 observations' rows are in
+// flight per 16-lane group.
+template <int J>
+__global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col, const float* __restrict__ W,
+                                                      const float* __restrict__ H, float* __restrict__ yhat) {
+    constexpr int D = 64 * J;
+    const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    if (u >= U) return;
+    float4 w[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) w[j] = *reinterpret_cast<const float4*>(W + (size_t)u * D + 4 * q16 + 64 * j);
+    const int64_t lo = ptr[u], hi = ptr[u + 1];
+    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+        const int64_t k = c0 + lane;
+        const int ci = (k < hi) ? col[k] : 0;
+        const int cnt = (int)min((int64_t)64, hi - c0);
+        const int nsteps = (cnt + 3) >> 2;
+        for (int st = 0; st < nsteps; st += 4) {
+            float4 h[4][J];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (st + v < nsteps) {
+                    const int i = __shfl(ci, 4 * (st + v) + g4);
+#pragma unroll
+                    for (int j = 0; j < J; ++j)
+                        h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * D + 4 * q16 + 64 * j);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (st + v < nsteps) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        s = fmaf(w[j].x, h[v][j].x, s);
+                        s = fmaf(w[j].y, h[v][j].y, s);
+                        s = fmaf(w[j].z, h[v][j].z, s);
+                        s = fmaf(w[j].w, h[v][j].w, s);
+                    }
+                    s += __shfl_xor(s, 8);
+                    s += __shfl_xor(s, 4);
+                    s += __shfl_xor(s, 2);
+                    s += __shfl_xor(s, 1);
+                    const int idx = 4 * (st + v) + g4;
+                    if (q16 == 0 && idx < cnt) yhat[c0 + idx] = s;
+                }
+            }
+        }
+    }
+}
+
 // Partial Gramian of one row chunk: part[chunk][f][q] = sum_{r in chunk} X[r][f] X[r][p0+q]
 // for f < d, q < ncols (columns q >= bw are zero).  Block = one wavefront owning a
 // 64 x (16*QT) output tile (4 x QT MFMA tiles).
@@ -105,12 +159,24 @@ __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const fl
             }
 }
 
-__global__ void k_gram_reduce(const float* __restrict__ part, int32_t nchunks, int64_t count, float* __restrict__ out32) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// out[e] = sum over chunks of part[c][e] in float64.  A block owns 16 outputs; its
+// 16 thread rows each sum every 16th chunk, and the 16 partial sums of an
+// output are then added in a fixed order.
+__global__ __launch_bounds__(256) void k_gram_reduce(const float* __restrict__ part, int32_t nchunks, int64_t count,
+                                                     float* __restrict__ out32) {
+    __shared__ double red[16][17];
+    const int o = threadIdx.x & 15, c = threadIdx.x >> 4;
+    const int64_t e = (int64_t)blockIdx.x * 16 + o;
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += (double)part[(size_t)c * count + e];
-    out32[e] = (float)s;
+    if (e < count)
+        for (int ch = c; ch < nchunks; ch += 16) s += (double)part[(size_t)ch * count + e];
+    red[c][o] = s;
+    __syncthreads();
+    if (c == 0 && e < count) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += red[k][o];
+        out32[e] = (float)t;
+    }
 }
 
 // Dmat = alpha0 * G[p0:p0+bw, 0:bw] + lambda I, identity on the padding; also
@@ -296,7 +362,16 @@ size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols) {
 void launch_predict(ials_ctx* c) {
     const SideIndex& us = c->side[IALS_SIDE_USER];
     if (c->U == 0 || c->nnz == 0) return;
-    if (c->d % 64 == 0)
+    if (c->d == 64)
+        hipLaunchKernelGGL(k_predict_rows<1>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
+                           c->H, c->yhat);
+    else if (c->d == 128)
+        hipLaunchKernelGGL(k_predict_rows<2>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
+                           c->H, c->yhat);
+    else if (c->d == 256)
+        hipLaunchKernelGGL(k_predict_rows<4>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
+                           c->H, c->yhat);
+    else if (c->d % 64 == 0)
         hipLaunchKernelGGL(k_predict<true>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col,
                            c->W, c->H, c->yhat);
     else
@@ -323,7 +398,7 @@ void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int
     else
         hipLaunchKernelGGL(k_gram_part<1>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
     const int64_t count = (int64_t)d * ncols;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 256)), dim3(256), 0, c->stream, c->gram_part, (int32_t)chunks,
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, c->stream, c->gram_part, (int32_t)chunks,
                        count, out);
     if (make_dmat)
         hipLaunchKernelGGL(k_make_dmat, dim3(nblk(std::max(c->B * c->B, (int)CUR_NUM), 256)), dim3(256), 0, c->stream,

@@ -68,6 +68,7 @@ struct ials_ctx {
     float* yhat = nullptr;       // [nnz] user-major order
     float* G = nullptr;          // [d * B] partial Gramian of the fixed side
     float* Dmat = nullptr;       // [B * B] alpha0 * G_pipi + lambda I (identity on padding)
+    float* dtiles = nullptr;     // [B * B + ...] the same in the MFMA accumulator layout
     float* R0 = nullptr;         // [max(U,I) * B] dense gradient term
     float* gram_part = nullptr;  // split-K partials
     size_t gram_part_floats = 0;
@@ -86,7 +87,34 @@ struct ials_ctx {
 
     std::string err;
     std::vector<void*> owned;  // every device allocation of this context
+
+    // per-kernel timing (HIP events on the stream), off by default
+    bool prof = false;
+    std::vector<hipEvent_t> prof_pool;   // 2 events per recorded launch
+    std::vector<int> prof_kind;          // family of each recorded launch
+    size_t prof_used = 0;
+    double prof_ms[IALS_K_NUM] = {};
+    int64_t prof_count[IALS_K_NUM] = {};
 };
+
+namespace ials {
+// Brackets the launches issued in its lifetime with events when profiling is on.
+struct ProfScope {
+    ials_ctx* c;
+    int kind;
+    size_t slot = (size_t)-1;
+    ProfScope(ials_ctx* c_, int kind_) : c(c_), kind(kind_) {
+        if (c->prof && 2 * (c->prof_used + 1) <= c->prof_pool.size()) {
+            slot = c->prof_used++;
+            c->prof_kind[slot] = kind;
+            (void)hipEventRecord(c->prof_pool[2 * slot], c->stream);
+        }
+    }
+    ~ProfScope() {
+        if (slot != (size_t)-1) (void)hipEventRecord(c->prof_pool[2 * slot + 1], c->stream);
+    }
+};
+}  // namespace ials
 
 namespace ials {
 

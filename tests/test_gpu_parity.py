@@ -149,3 +149,35 @@ def test_invalid_observations_rejected():
     p.item[0] = 40  # out of range
     with pytest.raises(IalsError, match="IALS_E_INVALID"):
         gpu_trainer(p)
+
+
+def test_ml20m_like_full_size_epoch1():
+    """Full-size workload (136k x 20k, 10M observations, d=128, b=64) in the launch
+    configuration the benchmark times: one epoch from the identical start."""
+    import time
+    p = synth.make_problem("ml20m_like")
+    say("ml20m_like generated")
+    tr = gpu_trainer(p)
+    L0, _ = tr.loss()
+    tr.epoch(1)
+    L1, _ = tr.loss()
+    Wg, Hg = host(tr.W), host(tr.H)
+    st = tr.stats()
+    tr.close()
+    say(f"gpu done, fallback rows {st['fallback_rows']}, segments {st['segments_user']}/{st['segments_item']}")
+    csr, _, _ = oracle_setup(p)
+    t = time.time()
+    W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1)
+    say(f"oracle epoch {time.time() - t:.1f}s")
+    Lr0 = oracle.loss(csr, p.W0, p.H0, p.alpha0, p.lam)
+    ew, eh, el = rel(Wg, W), rel(Hg, H), abs(L1 - losses[0]) / losses[0]
+    say(f"ml20m_like epoch 1: W {ew:.2e} H {eh:.2e} loss {el:.2e} (L0 {L0:.6e} vs {Lr0:.6e})")
+    assert abs(L0 - Lr0) <= 1e-10 * Lr0
+    assert ew < 1e-4 and eh < 1e-4 and el < 1e-6
+
+
+def test_forced_fallback_on_long_rows_full_blocks():
+    # vector-loaded (column-permuted) blocks with segmented rows, every row redone in float64
+    p = synth.small_problem(51, 3000, 120, 60_000, 64, 32, labels=True, zipf_s=0.8, std=0.1)
+    st = _epoch_check(p, 1, 1e-4, 1e-6, chol_fallback_ratio=1.0)
+    assert st["fallback_rows"] == (p.num_users + p.num_items) * 2 and st["segments_item"] > 0
