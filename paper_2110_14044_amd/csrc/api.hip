@@ -107,7 +107,7 @@ ials_status run_pass(ials_ctx* c, int side, int32_t blk) {
         ials::ProfScope ps(c, IALS_K_DENSE_USER + side);
         ials::launch_dense(c, X, n, p0, bw);
     }
-    ials::launch_sweep(c, side, p0, bw);
+    ials::launch_sweep(c, side, blk);
     c->passes += 1;
     IALS_HIP_TRY(c, hipGetLastError());
     return IALS_OK;
@@ -194,6 +194,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     }
     TRY_ALLOC(c, is.slot, sizeof(int32_t) * nnz);
     TRY_ALLOC(c, c->yhat, sizeof(float) * nnz);
+    TRY_ALLOC(c, c->pred, sizeof(float) * nnz);
 
     // observations on the device (temporary copies when they come from the host)
     const int32_t *du = S->user, *di = S->item;
@@ -240,7 +241,6 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     TRY_ALLOC(c, c->Dmat, sizeof(float) * c->B * c->B);
     TRY_ALLOC(c, c->dtiles, sizeof(float) * 256 * (c->B / 16) * (c->B / 16 + 1) / 2);
     TRY_ALLOC(c, c->R0, sizeof(float) * nmax * c->B);
-    TRY_ALLOC(c, c->delta, sizeof(float) * nmax * c->B);
     TRY_ALLOC(c, c->fb_list, sizeof(int32_t) * nmax);
     size_t gp = 0;
     for (int32_t n : {c->U, c->I})
@@ -257,7 +257,8 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     TRY_ALLOC(c, c->gram64, sizeof(double) * 2 * dd);
     TRY_ALLOC(c, c->loss_out, sizeof(double) * 4);
 
-    ials::launch_predict(c);
+    c->cur_block = 0;
+    ials::launch_predict(c, 0, false, c->yhat);
     TRY_HIP_CREATE(hipGetLastError());
     TRY_HIP_CREATE(hipStreamSynchronize(c->stream));
     guard.armed = false;
@@ -323,7 +324,7 @@ ials_status ials_block_sweep(ials_ctx* c, int32_t side, int32_t block) {
 
 ials_status ials_refresh_predictions(ials_ctx* c) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
-    ials::launch_predict(c);
+    ials::launch_predict(c, c->cur_block, false, c->yhat);
     IALS_HIP_TRY(c, hipGetLastError());
     return IALS_OK;
 }
@@ -335,7 +336,8 @@ ials_status ials_epoch(ials_ctx* c, int32_t n_epochs) {
     for (int32_t t = 0; t < n_epochs; ++t) {
         {
             ials::ProfScope ps(c, IALS_K_PREDICT);
-            ials::launch_predict(c);
+            ials::launch_predict(c, 0, false, c->yhat);
+            c->cur_block = 0;
         }
         for (int32_t blk = 0; blk < nblocks; ++blk) {
             ials_status s = run_pass(c, IALS_SIDE_USER, blk);
@@ -393,8 +395,11 @@ ials_status ials_get_csr(ials_ctx* c, int32_t side, int64_t* row_ptr, int32_t* c
 ials_status ials_get_predictions(ials_ctx* c, float* out_host) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
     if (!out_host) return fail(c, IALS_E_INVALID, "null output");
-    if (c->nnz > 0)
-        IALS_HIP_TRY(c, hipMemcpyAsync(out_host, c->yhat, sizeof(float) * c->nnz, hipMemcpyDeviceToHost, c->stream));
+    if (c->nnz > 0) {
+        ials::launch_predict(c, c->cur_block, true, c->pred);
+        IALS_HIP_TRY(c, hipGetLastError());
+        IALS_HIP_TRY(c, hipMemcpyAsync(out_host, c->pred, sizeof(float) * c->nnz, hipMemcpyDeviceToHost, c->stream));
+    }
     IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
     return IALS_OK;
 }

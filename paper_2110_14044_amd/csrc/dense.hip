@@ -21,11 +21,16 @@ __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// One wavefront per user; 16 lanes per observation, 4 observations at a time.
-template <bool VEC4>
+// Prediction cache relative to a block pi = [p0, p0+bw) (eq. 1 split in two parts):
+//   inside == false:  out_k = sum over f outside pi of w_u[f] h_i[f]
+//   inside == true:   out_k = base_k + sum over f inside pi of w_u[f] h_i[f]
+// With inside == false this is the cache a pass of block pi starts from
+// (yhat = out + <w_{u,pi}, h_{i,pi}>); with inside == true it turns the cache back
+// into yhat.  One wavefront per user; 16 lanes per observation, 4 at a time.
 __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int64_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ col, const float* __restrict__ W,
-                                                 const float* __restrict__ H, float* __restrict__ yhat) {
+                                                 const float* __restrict__ H, int32_t p0, int32_t bw, bool inside,
+                                                 const float* __restrict__ base, float* __restrict__ out) {
     const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     if (u >= U) return;
@@ -36,40 +41,41 @@ __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int
         const bool v = k < hi;
         const float* h = H + (size_t)(v ? col[k] : 0) * d;
         float s = 0.f;
-        if (VEC4) {
-            for (int f = 4 * q16; f < d; f += 64) {
-                const float4 a = *reinterpret_cast<const float4*>(w + f);
-                const float4 b = *reinterpret_cast<const float4*>(h + f);
-                s = fmaf(a.x, b.x, s);
-                s = fmaf(a.y, b.y, s);
-                s = fmaf(a.z, b.z, s);
-                s = fmaf(a.w, b.w, s);
-            }
-        } else {
-            for (int f = q16; f < d; f += 16) s = fmaf(w[f], h[f], s);
+        for (int f = q16; f < d; f += 16) {
+            const bool in = f >= p0 && f < p0 + bw;
+            if (in == inside) s = fmaf(w[f], h[f], s);
         }
         s += __shfl_xor(s, 8);
         s += __shfl_xor(s, 4);
         s += __shfl_xor(s, 2);
         s += __shfl_xor(s, 1);
-        if (v && q16 == 0) yhat[k] = s;
+        if (v && q16 == 0) out[k] = inside ? base[k] + s : s;
     }
 }
 
-// Same computation for d = 64*J with the row held in registers: the partner
-// ids of 64 observations are loaded at once and 4 observations' rows are in
-// flight per 16-lane group.
+// Same computation for d = 64*J with the row held in registers (the excluded or
+// included columns are masked once per row): the partner ids of 64 observations
+// are loaded at once and 4 observations' rows are in flight per 16-lane group.
 template <int J>
 __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ W,
-                                                      const float* __restrict__ H, float* __restrict__ yhat) {
+                                                      const float* __restrict__ H, int32_t p0, int32_t bw, bool inside,
+                                                      const float* __restrict__ base, float* __restrict__ out) {
     constexpr int D = 64 * J;
     const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     if (u >= U) return;
     float4 w[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) w[j] = *reinterpret_cast<const float4*>(W + (size_t)u * D + 4 * q16 + 64 * j);
+    for (int j = 0; j < J; ++j) {
+        float4 v = *reinterpret_cast<const float4*>(W + (size_t)u * D + 4 * q16 + 64 * j);
+        const int f = 4 * q16 + 64 * j;
+        v.x = ((f + 0 >= p0 && f + 0 < p0 + bw) == inside) ? v.x : 0.f;
+        v.y = ((f + 1 >= p0 && f + 1 < p0 + bw) == inside) ? v.y : 0.f;
+        v.z = ((f + 2 >= p0 && f + 2 < p0 + bw) == inside) ? v.z : 0.f;
+        v.w = ((f + 3 >= p0 && f + 3 < p0 + bw) == inside) ? v.w : 0.f;
+        w[j] = v;
+    }
     const int64_t lo = ptr[u], hi = ptr[u + 1];
     for (int64_t c0 = lo; c0 < hi; c0 += 64) {
         const int64_t k = c0 + lane;
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
                     s += __shfl_xor(s, 2);
                     s += __shfl_xor(s, 1);
                     const int idx = 4 * (st + v) + g4;
-                    if (q16 == 0 && idx < cnt) yhat[c0 + idx] = s;
+                    if (q16 == 0 && idx < cnt) out[c0 + idx] = inside ? base[c0 + idx] + s : s;
                 }
             }
         }
@@ -359,24 +365,25 @@ size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols) {
     return (size_t)std::max<int64_t>(chunks, 1) * d * ncols;
 }
 
-void launch_predict(ials_ctx* c) {
+// inside == false: c->yhat becomes the cache relative to block blk; inside == true:
+// out = c->yhat + the block's part (the predictions themselves).
+void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
     const SideIndex& us = c->side[IALS_SIDE_USER];
     if (c->U == 0 || c->nnz == 0) return;
+    const int32_t p0 = blk * c->b, bw = std::min(c->b, c->d - p0);
+    const unsigned g = nblk(c->U, 4);
     if (c->d == 64)
-        hipLaunchKernelGGL(k_predict_rows<1>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
-                           c->H, c->yhat);
+        hipLaunchKernelGGL(k_predict_rows<1>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
+                           bw, inside, c->yhat, out);
     else if (c->d == 128)
-        hipLaunchKernelGGL(k_predict_rows<2>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
-                           c->H, c->yhat);
+        hipLaunchKernelGGL(k_predict_rows<2>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
+                           bw, inside, c->yhat, out);
     else if (c->d == 256)
-        hipLaunchKernelGGL(k_predict_rows<4>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W,
-                           c->H, c->yhat);
-    else if (c->d % 64 == 0)
-        hipLaunchKernelGGL(k_predict<true>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col,
-                           c->W, c->H, c->yhat);
+        hipLaunchKernelGGL(k_predict_rows<4>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
+                           bw, inside, c->yhat, out);
     else
-        hipLaunchKernelGGL(k_predict<false>, dim3(nblk(c->U, 4)), dim3(256), 0, c->stream, c->U, c->d, us.ptr,
-                           us.col, c->W, c->H, c->yhat);
+        hipLaunchKernelGGL(k_predict, dim3(g), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col, c->W, c->H, p0, bw,
+                           inside, c->yhat, out);
 }
 
 // out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw); with make_dmat

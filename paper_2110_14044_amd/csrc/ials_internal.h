@@ -65,7 +65,9 @@ struct ials_ctx {
 
     // owned
     ials::SideIndex side[2];
-    float* yhat = nullptr;       // [nnz] user-major order
+    float* yhat = nullptr;       // [nnz] user-major: prediction minus the part of block cur_block
+    int32_t cur_block = 0;       // the block the prediction cache is relative to
+    float* pred = nullptr;       // [nnz] predictions materialised on request
     float* G = nullptr;          // [d * B] partial Gramian of the fixed side
     float* Dmat = nullptr;       // [B * B] alpha0 * G_pipi + lambda I (identity on padding)
     float* dtiles = nullptr;     // [B * B + ...] the same in the MFMA accumulator layout
@@ -73,7 +75,6 @@ struct ials_ctx {
     float* gram_part = nullptr;  // split-K partials
     size_t gram_part_floats = 0;
     float* seg_part = nullptr;   // per-segment partial Hessian + gradient
-    float* delta = nullptr;      // [max(U,I) * B]
     int32_t* fb_list = nullptr;  // [max(U,I)]
     int32_t* cursors = nullptr;  // [CUR_NUM]
     unsigned long long* counters = nullptr;  // [CNT_NUM]
@@ -121,11 +122,11 @@ namespace ials {
 // Host-side launchers (implemented in the .hip files).
 ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_item, const float* d_y,
                         const float* d_a);
-void launch_predict(ials_ctx* c);
+void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out);
 void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols,
                          float* out, bool make_dmat);
 void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw);
-void launch_sweep(ials_ctx* c, int side, int32_t p0, int32_t bw);
+void launch_sweep(ials_ctx* c, int side, int32_t blk);
 ials_status launch_loss(ials_ctx* c);
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
 size_t seg_part_floats_per_segment(int32_t B);

@@ -3,17 +3,24 @@
 // For every row r of the side being updated (users, or items) and the block
 // pi = [p0, p0+bw) padded to B = 16*NT columns:
 //   T      = X_other[partners(r), pi]            gathered straight from the embedding table
+//   yhat_k = c_k + <x_{r,pi}, T_k>               (c: prediction cache without block pi)
 //   Hess   = alpha0 G_pipi + lambda I + T^T diag(a) T   (MFMA f32 16x16x4, lower tiles only)
 //   grad   = R0[r] + T^T (a (yhat - y))          (R0 = alpha0 x_r G^pi + lambda x_{r,pi}, precomputed)
 //   delta  = Hess^-1 grad                         (blocked Cholesky on the accumulator tiles)
-//   x_{r,pi} -= delta;  yhat_k -= <delta, T_k>   (the delta update of the prediction cache)
+//   x_{r,pi} -= delta
 //
-// One wavefront owns one row at a time and takes rows from a work queue in
-// order of decreasing length, so rows of very different lengths share the GPU
-// evenly.  Rows longer than kSegLen observations are split into segments:
-// k_sweep_seg accumulates each segment's partial Hessian and gradient, the row
-// kernel adds them in segment order (a fixed order, so results are bitwise
-// reproducible), solves, and k_patch_seg patches yhat segment by segment.
+// The prediction cache holds, per observation, the prediction minus the part of
+// the current block (c = yhat - <x_pi, o_pi>).  It does not change while block
+// pi is being optimised, so no pass has to patch it: each pass forms yhat from
+// c and the two rows it already holds.  The first pass of a new block pi' moves
+// the cache: yhat = c + <x_pi, o_pi> (the old block, one more gather) and
+// c' = yhat - <x_pi', o_pi'>.  This is the same iteration as the delta update of
+// the cached predictions in Alg. 3 (the predictions are equal in exact arithmetic).
+//
+// Rows longer than kSegLen observations are split into segments: k_sweep_seg
+// accumulates each segment's partial Hessian and gradient, the row kernel adds
+// them in segment order (a fixed order, so results are bitwise reproducible) and
+// solves.
 // A row whose float32 Cholesky pivots fall below tau * (largest pivot), or are
 // not positive, is redone from scratch in float64 by k_sweep_fallback.
 //
@@ -35,16 +42,18 @@ namespace {
 struct SweepArgs {
     const int64_t* ptr;
     const int32_t* col;
-    const int32_t* slot;  // yhat position per observation (null: identity)
+    const int32_t* slot;  // cache position per observation (null: identity)
     const float* y;       // labels in this side's order (null: ones)
     const float* a;       // weights in this side's order (null: ones)
     float* X;             // side being updated, N x d
     const float* Xo;      // fixed side
-    float* yhat;
+    float* cache;         // prediction cache (user-major positions)
     const float* R0;      // N x B
     const float* Dmat;    // B x B
     float* dtiles;        // the Hessian start in accumulator layout (NTL x 64 x 4)
     int32_t d, p0, bw, nrows;
+    int32_t pc, bwc;      // the block the cache is relative to when the pass starts
+    int32_t cur_full;     // that block is loaded with vector loads
     const int32_t* order;
     const int32_t* seg_first;
     const int32_t* seg_row;
@@ -52,11 +61,11 @@ struct SweepArgs {
     const int64_t* seg_hi;
     int32_t nseg;
     float* seg_part;
-    float* delta;
     int32_t* fb_list;
     int32_t* cursors;
     unsigned long long* counters;
     float tau;
+    int32_t rows_batch;   // 0: static round-robin rows; 1: rows from the shared queue
 };
 
 __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
@@ -70,10 +79,18 @@ __device__ inline void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
+// Next item from a work queue shared by all wavefronts.
 __device__ inline int queue_next(int32_t* cursor, int lane) {
     int it = 0;
     if (lane == 0) it = atomicAdd(cursor, 1);
     return __builtin_amdgcn_readfirstlane(it);
+}
+__device__ inline float sum16(float s) {
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    return s;
 }
 
 template <int NT>
@@ -86,72 +103,105 @@ constexpr int seg_stride() { return ntiles<NT>() * 256 + 16 * NT; }
 template <int NT, bool FULL>
 __host__ __device__ constexpr int colmap(int p) { return FULL ? NT * (p & 15) + (p >> 4) : p; }
 
-// x[t] = X_other[i][p0 + colmap(16 t + q16)], 0 outside the block.
-template <int NT, bool FULL>
-__device__ inline void gather_row(const SweepArgs& A, int i, int q16, float* x) {
-    const float* xr = A.Xo + (size_t)i * A.d + A.p0;
-    if constexpr (FULL && NT == 4) {
+// x[t] = X[i][p0 + column of position 16 t + q16], 0 outside the block [p0, p0+bw).
+// Vector mode: lane q16 takes the NT consecutive columns NT*q16 .. NT*q16+NT-1.
+template <int NT, bool VEC>
+__device__ inline void load_cols(const float* __restrict__ X, int d, int i, int p0, int bw, int q16, float* x) {
+    const float* xr = X + (size_t)i * d + p0;
+    if constexpr (VEC && NT == 4) {
         const float4 v = *reinterpret_cast<const float4*>(xr + 4 * q16);
         x[0] = v.x;
         x[1] = v.y;
         x[2] = v.z;
         x[3] = v.w;
-    } else if constexpr (FULL && NT == 2) {
+    } else if constexpr (VEC && NT == 2) {
         const float2 v = *reinterpret_cast<const float2*>(xr + 2 * q16);
         x[0] = v.x;
         x[1] = v.y;
-    } else if constexpr (FULL && NT == 1) {
+    } else if constexpr (VEC && NT == 1) {
         x[0] = xr[q16];
     } else {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int c = 16 * t + q16;
-            const float v = xr[c < A.bw ? c : A.bw - 1];
-            x[t] = (c < A.bw) ? v : 0.f;
+            const float v = xr[c < bw ? c : bw - 1];
+            x[t] = (c < bw) ? v : 0.f;
         }
     }
 }
 
+// The current block of the cache, read in vector mode when it is a full block.
+template <int NT>
+__device__ inline void load_cur(const SweepArgs& A, const float* X, int i, int q16, float* x) {
+    if (A.cur_full)
+        load_cols<NT, (NT != 3)>(X, A.d, i, A.pc, A.bwc, q16, x);
+    else
+        load_cols<NT, false>(X, A.d, i, A.pc, A.bwc, q16, x);
+}
+
 // acc (lower tiles, MFMA D layout, p order) += T^T diag(a) T and gp[t] (position
-// 16t+q16, this lane group's share) += T^T (a (yhat - y)) over observations [lo, hi).
-template <int NT, bool FULL>
-__device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, floatx4* acc, float* gp, int lane) {
+// 16t+q16, this lane group's share) += T^T (a (yhat - y)) over observations
+// [lo, hi) of one row whose own block values are own[] (block pi) and ownc[]
+// (the cache's block, TRANS only).  With TRANS the cache entries are moved to pi.
+template <int NT, bool FULL, bool TRANS>
+__device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
+                                  floatx4* acc, float* gp, int lane) {
     const int q16 = lane & 15, g4 = lane >> 4;
     for (int64_t c0 = lo; c0 < hi; c0 += 64) {
         const int64_t k = c0 + lane;
         const bool v = k < hi;
-        int ci = 0;
-        float res = 0.f, aw = 0.f;
+        int ci = 0, si = 0;
+        float cv = 0.f, yv = 1.f, av = 1.f;
         if (v) {
             ci = A.col[k];
-            const int64_t s = A.slot ? (int64_t)A.slot[k] : k;
-            const float ak = A.a ? A.a[k] : 1.f;
-            const float yk = A.y ? A.y[k] : 1.f;
-            res = ak * (A.yhat[s] - yk);
-            aw = ak;
+            si = A.slot ? A.slot[k] : (int)k;
+            cv = A.cache[si];
+            if (A.y) yv = A.y[k];
+            if (A.a) av = A.a[k];
         }
-        const int nsteps = ((int)std::min<int64_t>(64, hi - c0) + 3) >> 2;
+        const int cnt = (int)std::min<int64_t>(64, hi - c0);
+        const int nsteps = (cnt + 3) >> 2;
         for (int st = 0; st < nsteps; st += 4) {
             const int nv = std::min(4, nsteps - st);
-            float x[4][NT], r4[4], a4[4];
+            float x[4][NT], xc[4][TRANS ? NT : 1];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (u < nv) {
-                    const int src = 4 * (st + u) + g4;
-                    const int i = __shfl(ci, src);
-                    r4[u] = __shfl(res, src);
-                    a4[u] = __shfl(aw, src);
-                    gather_row<NT, FULL>(A, i, q16, x[u]);
+                    const int i = __shfl(ci, 4 * (st + u) + g4);
+                    load_cols<NT, FULL>(A.Xo, A.d, i, A.p0, A.bw, q16, x[u]);
+                    if constexpr (TRANS) load_cur<NT>(A, A.Xo, i, q16, xc[u]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (u < nv) {
+                    const int src = 4 * (st + u) + g4;
+                    const bool valid = src < cnt;
+                    const float ck = __shfl(cv, src);
+                    const float yk = A.y ? __shfl(yv, src) : 1.f;
+                    // every lane takes part in the shuffles (a source lane must be active)
+                    const float ak_all = A.a ? __shfl(av, src) : 1.f;
+                    const float ak = valid ? ak_all : 0.f;
+                    float sp = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
+                    sp = sum16(sp);
+                    float yh = ck + sp;
+                    if constexpr (TRANS) {
+                        float sc = 0.f;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) sc = fmaf(xc[u][t], ownc[t], sc);
+                        sc = sum16(sc);
+                        yh = ck + sc;
+                        const int sk = __shfl(si, src);
+                        if (q16 == 0 && valid) A.cache[sk] = yh - sp;
+                    }
+                    const float rk = ak * (yh - yk);
                     float xa[NT];
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        gp[t] = fmaf(r4[u], x[u][t], gp[t]);
-                        xa[t] = a4[u] * x[u][t];
+                        gp[t] = fmaf(rk, x[u][t], gp[t]);
+                        xa[t] = ak * x[u][t];
                     }
                     int id = 0;
 #pragma unroll
@@ -167,61 +217,27 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, fl
     }
 }
 
-// yhat_k -= <delta, x_other[k, pi]> over observations [lo, hi); dl[t] = delta at position 16t + q16.
-template <int NT, bool FULL>
-__device__ inline void patch(const SweepArgs& A, int64_t lo, int64_t hi, const float* dl, int lane) {
-    const int q16 = lane & 15, g4 = lane >> 4;
-    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
-        const int64_t k = c0 + lane;
-        const bool v = k < hi;
-        const int ci = v ? A.col[k] : 0;
-        const int si = v ? (A.slot ? A.slot[k] : (int)k) : 0;
-        const int cnt = (int)std::min<int64_t>(64, hi - c0);
-        const int nsteps = (cnt + 3) >> 2;
-        for (int st = 0; st < nsteps; st += 4) {
-            const int nv = std::min(4, nsteps - st);
-            float x[4][NT];
-            int sd[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u < nv) {
-                    const int src = 4 * (st + u) + g4;
-                    const int i = __shfl(ci, src);
-                    sd[u] = __shfl(si, src);
-                    gather_row<NT, FULL>(A, i, q16, x[u]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u < nv) {
-                    float dot = 0.f;
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) dot = fmaf(x[u][t], dl[t], dot);
-                    dot += __shfl_xor(dot, 8);
-                    dot += __shfl_xor(dot, 4);
-                    dot += __shfl_xor(dot, 2);
-                    dot += __shfl_xor(dot, 1);
-                    if (q16 == 0 && 4 * (st + u) + g4 < cnt) A.yhat[sd[u]] -= dot;
-                }
-            }
-        }
-    }
+// Own block values of row r: own[t] at block pi (this pass's column order),
+// ownc[t] at the cache's block (TRANS only).
+template <int NT, bool FULL, bool TRANS>
+__device__ inline void load_own(const SweepArgs& A, int r, int q16, float* own, float* ownc) {
+    load_cols<NT, FULL>(A.X, A.d, r, A.p0, A.bw, q16, own);
+    if constexpr (TRANS) load_cur<NT>(A, A.X, r, q16, ownc);
 }
 
-template <int NT, bool FULL>
+template <int NT, bool FULL, bool TRANS>
 __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
     constexpr int NTL = ntiles<NT>();
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
-    for (;;) {
-        const int it = queue_next(&A.cursors[CUR_SEGS], lane);
-        if (it >= A.nseg) break;
+    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < A.nseg; it += gridDim.x * 4) {
         floatx4 acc[NTL];
-        float gp[NT];
+        float gp[NT], own[NT], ownc[TRANS ? NT : 1];
 #pragma unroll
         for (int id = 0; id < NTL; ++id) acc[id] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < NT; ++t) gp[t] = 0.f;
-        accumulate<NT, FULL>(A, A.seg_lo[it], A.seg_hi[it], acc, gp, lane);
+        load_own<NT, FULL, TRANS>(A, A.seg_row[it], q16, own, ownc);
+        accumulate<NT, FULL, TRANS>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             gp[t] += __shfl_xor(gp[t], 16);
@@ -244,10 +260,8 @@ template <int NT>
 constexpr int panel_rows() { return 16 * NT * (NT + 1) / 2; }
 template <int NT>
 __host__ __device__ constexpr int panel_row0(int K) { return 16 * (K * NT - K * (K - 1) / 2); }
-// LDS floats of k_sweep_rows per wavefront: the packed panels and two 64-entry
-// broadcast columns.
 template <int NT>
-constexpr int rows_lds_floats_per_wave() { return panel_rows<NT>() * kPS + 128; }
+constexpr int rows_lds_floats_per_wave() { return panel_rows<NT>() * kPS; }
 template <int NT>
 constexpr int rows_lds_floats() { return 4 * rows_lds_floats_per_wave<NT>(); }
 
@@ -265,20 +279,22 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
     dtiles[e] = Dmat[colmap<NT, FULL>(16 * ti + 4 * (lq >> 4) + j) * B + colmap<NT, FULL>(16 * tj + (lq & 15))];
 }
 
-template <int NT, bool FULL>
+template <int NT, bool FULL, bool TRANS>
 __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     float* pan = lds_all + wave * rows_lds_floats_per_wave<NT>();
-    float* colA = pan + panel_rows<NT>() * kPS;
-    float* colG = colA + 64;
     const int my_col = colmap<NT, FULL>(lane < B ? lane : 0);
 
+    // rows_batch == 0: rows are dealt round-robin in the length order (sides whose rows
+    // are all short); otherwise each wavefront takes the next row from a shared queue.
+    int it = A.rows_batch ? 0 : blockIdx.x * 4 + wave;
     for (;;) {
-        const int it = queue_next(&A.cursors[CUR_ROWS], lane);
+        if (A.rows_batch) it = queue_next(&A.cursors[CUR_ROWS], lane);
         if (it >= A.nrows) break;
         const int r = A.order[it];
+        if (!A.rows_batch) it += gridDim.x * 4;
         const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
         floatx4 acc[NTL];
 #pragma unroll
@@ -288,7 +304,9 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         for (int t = 0; t < NT; ++t) gp[t] = 0.f;
         const int sf = A.seg_first[r];
         if (sf < 0) {
-            accumulate<NT, FULL>(A, lo, hi, acc, gp, lane);
+            float own[NT], ownc[TRANS ? NT : 1];
+            load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
+            accumulate<NT, FULL, TRANS>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
@@ -351,24 +369,15 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
                 const int k = 16 * K + kk;
-                colA[lane] = p[kk];
-                colG[lane] = g;
-                wave_lds_fence();
-                const float piv = colA[k];
-                const float gk = colG[k];
+                // column k of the panel lives in register p[kk] across the lanes
+                const float piv = readlane(p[kk], k);
+                const float gk = readlane(g, k);
                 const float rs = (piv > 0.f) ? __builtin_amdgcn_rsqf(piv) : 0.f;
                 const float t = (ln > k) ? p[kk] * (rs * rs) : 0.f;
                 g = fmaf(-t, gk, g);
 #pragma unroll
-                for (int j4 = (kk + 1) / 4; j4 < 4; ++j4) {
-                    const float4 c = *reinterpret_cast<const float4*>(colA + 16 * K + 4 * j4);
-                    if (4 * j4 + 0 > kk) p[4 * j4 + 0] = fmaf(-t, c.x, p[4 * j4 + 0]);
-                    if (4 * j4 + 1 > kk) p[4 * j4 + 1] = fmaf(-t, c.y, p[4 * j4 + 1]);
-                    if (4 * j4 + 2 > kk) p[4 * j4 + 2] = fmaf(-t, c.z, p[4 * j4 + 2]);
-                    if (4 * j4 + 3 > kk) p[4 * j4 + 3] = fmaf(-t, c.w, p[4 * j4 + 3]);
-                }
+                for (int jj = kk + 1; jj < 16; ++jj) p[jj] = fmaf(-t, readlane(p[kk], 16 * K + jj), p[jj]);
                 p[kk] *= rs;
-                wave_lds_fence();
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (mine) {
@@ -417,7 +426,6 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
                 A.fb_list[pos] = r;
             }
-            if (sf >= 0 && lane < B) A.delta[(size_t)r * B + lane] = 0.f;
             continue;
         }
         g *= dinv;  // y = L^-1 grad
@@ -445,42 +453,20 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         wave_lds_fence();
         // g (lane p) = delta at block column colmap(p)
         if (lane < B && my_col < A.bw) A.X[(size_t)r * A.d + A.p0 + my_col] -= g;
-        if (sf >= 0) {
-            if (lane < B) A.delta[(size_t)r * B + lane] = g;
-            continue;
-        }
-        float dl[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) dl[t] = __shfl(g, 16 * t + q16);
-        patch<NT, FULL>(A, lo, hi, dl, lane);
-    }
-}
-
-template <int NT, bool FULL>
-__global__ __launch_bounds__(256) void k_patch_seg(SweepArgs A) {
-    constexpr int B = 16 * NT;
-    const int lane = threadIdx.x & 63, q16 = lane & 15;
-    for (;;) {
-        const int it = queue_next(&A.cursors[CUR_PATCH], lane);
-        if (it >= A.nseg) break;
-        const int r = A.seg_row[it];
-        float dl[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) dl[t] = A.delta[(size_t)r * B + 16 * t + q16];
-        patch<NT, FULL>(A, A.seg_lo[it], A.seg_hi[it], dl, lane);
     }
 }
 
 // Float64 redo of rows whose float32 factorisation was rejected: the Hessian and
-// gradient are re-accumulated from the gathered rows in float64, factored and
-// solved in float64; the row is then updated and (short rows) its yhat patched.
-template <int NT, bool FULL>
+// gradient are re-accumulated from the gathered rows in float64 (with the cache
+// already moved to this block by the pass), factored and solved in float64, and
+// the row is updated.
+template <int NT>
 __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
     constexpr int B = 16 * NT;
     constexpr int CH = 32;
     __shared__ double Hm[B][B + 1];
     __shared__ double xs[CH][B];
-    __shared__ double gv[B];
+    __shared__ double gv[B], own[B];
     __shared__ double rs[CH], ws[CH];
     __shared__ int ok;
     const int tid = threadIdx.x;
@@ -489,7 +475,10 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
         const int r = A.fb_list[idx];
         const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
         for (int e = tid; e < B * B; e += 256) Hm[e / B][e % B] = (double)A.Dmat[e];
-        if (tid < B) gv[tid] = (double)A.R0[(size_t)r * B + tid];
+        if (tid < B) {
+            gv[tid] = (double)A.R0[(size_t)r * B + tid];
+            own[tid] = tid < A.bw ? (double)A.X[(size_t)r * A.d + A.p0 + tid] : 0.0;
+        }
         if (tid == 0) ok = 1;
         __syncthreads();
         for (int64_t c0 = lo; c0 < hi; c0 += CH) {
@@ -498,6 +487,7 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
                 const int64_t k = c0 + j;
                 xs[j][c] = (k < hi && c < A.bw) ? (double)A.Xo[(size_t)A.col[k] * A.d + A.p0 + c] : 0.0;
             }
+            __syncthreads();
             if (tid < CH) {
                 const int64_t k = c0 + tid;
                 double res = 0.0, w = 0.0;
@@ -505,7 +495,9 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
                     const int64_t s = A.slot ? (int64_t)A.slot[k] : k;
                     const double ak = A.a ? (double)A.a[k] : 1.0;
                     const double yk = A.y ? (double)A.y[k] : 1.0;
-                    res = ak * ((double)A.yhat[s] - yk);
+                    double yh = (double)A.cache[s];
+                    for (int c = 0; c < A.bw; ++c) yh += own[c] * xs[tid][c];
+                    res = ak * (yh - yk);
                     w = ak;
                 }
                 rs[tid] = res;
@@ -560,29 +552,18 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
         }
         __syncthreads();
         if (tid < A.bw) A.X[(size_t)r * A.d + A.p0 + tid] -= (float)gv[tid];
-        if (A.seg_first[r] >= 0) {
-            if (tid < B) A.delta[(size_t)r * B + tid] = (float)gv[colmap<NT, FULL>(tid)];
-        } else {
-            for (int64_t k = lo + tid; k < hi; k += 256) {
-                const float* xr = A.Xo + (size_t)A.col[k] * A.d + A.p0;
-                double dot = 0.0;
-                for (int c = 0; c < A.bw; ++c) dot += gv[c] * (double)xr[c];
-                const int64_t s = A.slot ? (int64_t)A.slot[k] : k;
-                A.yhat[s] -= (float)dot;
-            }
-        }
         __syncthreads();
     }
 }
 
-template <int NT, bool FULL>
+template <int NT, bool FULL, bool TRANS>
 void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
     hipStream_t st = c->stream;
     const unsigned max_blocks = (unsigned)c->num_cu * 8;
     if (s.nseg > 0) {
         ProfScope ps(c, IALS_K_SEG_USER + sd);
-        hipLaunchKernelGGL((k_sweep_seg<NT, FULL>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)), dim3(256),
-                           0, st, args);
+        hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
+                           dim3(256), 0, st, args);
     }
     if (s.nrows > 0) {
         const size_t lds = sizeof(float) * rows_lds_floats<NT>();
@@ -590,30 +571,47 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
                            args.dtiles);
         {
             ProfScope ps(c, IALS_K_ROWS_USER + sd);
-            hipLaunchKernelGGL((k_sweep_rows<NT, FULL>), dim3(std::min<unsigned>(max_blocks, (s.nrows + 3) / 4)),
-                               dim3(256), lds, st, args);
+            // static dealing: exactly the blocks that are resident at once
+            static int resident = 0;
+            if (resident == 0) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS>, 256, lds) !=
+                        hipSuccess ||
+                    nb < 1)
+                    nb = 2;
+                resident = nb;
+            }
+            const unsigned rows_blocks = args.rows_batch ? max_blocks : (unsigned)(c->num_cu * resident);
+            hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS>),
+                               dim3(std::min<unsigned>(rows_blocks, (s.nrows + 3) / 4)), dim3(256), lds, st, args);
         }
         ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
-        hipLaunchKernelGGL((k_sweep_fallback<NT, FULL>), dim3((unsigned)c->num_cu), dim3(256), 0, st, args);
-    }
-    if (s.nseg > 0) {
-        ProfScope ps(c, IALS_K_PATCH_USER + sd);
-        hipLaunchKernelGGL((k_patch_seg<NT, FULL>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)), dim3(256),
-                           0, st, args);
+        hipLaunchKernelGGL((k_sweep_fallback<NT>), dim3((unsigned)c->num_cu), dim3(256), 0, st, args);
     }
 }
 
 template <int NT>
-void launch_sweep_full_or_not(ials_ctx* c, const SweepArgs& A, const SideIndex& s, int sd) {
+bool vec_ok(const SweepArgs& A, int p0, int bw, const float* X) {
     constexpr int B = 16 * NT;
-    const int vec = (NT == 3) ? 0 : NT;
-    bool full = vec > 0 && A.bw == B && (A.d % vec == 0) && (A.p0 % vec == 0) &&
-                ((reinterpret_cast<uintptr_t>(A.Xo) % (4 * vec)) == 0);
-    if constexpr (NT == 3) full = false;
-    if (full)
-        launch_sweep_nt<NT, true>(c, A, s, sd);
-    else
-        launch_sweep_nt<NT, false>(c, A, s, sd);
+    if (NT == 3) return false;
+    return bw == B && (A.d % NT == 0) && (p0 % NT == 0) && ((reinterpret_cast<uintptr_t>(X) % (4 * NT)) == 0);
+}
+
+template <int NT>
+void launch_sweep_b(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
+    const bool full = vec_ok<NT>(A, A.p0, A.bw, A.Xo) && vec_ok<NT>(A, A.p0, A.bw, A.X);
+    A.cur_full = vec_ok<NT>(A, A.pc, A.bwc, A.Xo) && vec_ok<NT>(A, A.pc, A.bwc, A.X);
+    if (full) {
+        if (trans)
+            launch_sweep_nt<NT, true, true>(c, A, s, sd);
+        else
+            launch_sweep_nt<NT, true, false>(c, A, s, sd);
+    } else {
+        if (trans)
+            launch_sweep_nt<NT, false, true>(c, A, s, sd);
+        else
+            launch_sweep_nt<NT, false, false>(c, A, s, sd);
+    }
 }
 
 }  // namespace
@@ -623,7 +621,8 @@ size_t seg_part_floats_per_segment(int32_t B) {
     return (size_t)(NT * (NT + 1) / 2) * 256 + (size_t)B;
 }
 
-void launch_sweep(ials_ctx* c, int sd, int32_t p0, int32_t bw) {
+// One pass of block blk on side sd; the cache moves to blk if it is relative to another block.
+void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     const SideIndex& s = c->side[sd];
     SweepArgs A;
     A.ptr = s.ptr;
@@ -633,13 +632,16 @@ void launch_sweep(ials_ctx* c, int sd, int32_t p0, int32_t bw) {
     A.a = s.a;
     A.X = sd == IALS_SIDE_USER ? c->W : c->H;
     A.Xo = sd == IALS_SIDE_USER ? c->H : c->W;
-    A.yhat = c->yhat;
+    A.cache = c->yhat;
     A.R0 = c->R0;
     A.Dmat = c->Dmat;
     A.dtiles = c->dtiles;
     A.d = c->d;
-    A.p0 = p0;
-    A.bw = bw;
+    A.p0 = blk * c->b;
+    A.bw = std::min(c->b, c->d - A.p0);
+    A.pc = c->cur_block * c->b;
+    A.bwc = std::min(c->b, c->d - A.pc);
+    A.cur_full = 0;
     A.nrows = s.nrows;
     A.order = s.order;
     A.seg_first = s.seg_first;
@@ -648,17 +650,20 @@ void launch_sweep(ials_ctx* c, int sd, int32_t p0, int32_t bw) {
     A.seg_hi = s.seg_hi;
     A.nseg = s.nseg;
     A.seg_part = c->seg_part;
-    A.delta = c->delta;
     A.fb_list = c->fb_list;
     A.cursors = c->cursors;
     A.counters = c->counters;
     A.tau = c->tau;
+    const int64_t avg = s.nrows > 0 ? c->nnz / s.nrows : 0;
+    A.rows_batch = avg < 256 ? 0 : 1;
+    const bool trans = blk != c->cur_block;
     switch (c->B) {
-        case 16: launch_sweep_full_or_not<1>(c, A, s, sd); break;
-        case 32: launch_sweep_full_or_not<2>(c, A, s, sd); break;
-        case 48: launch_sweep_full_or_not<3>(c, A, s, sd); break;
-        default: launch_sweep_full_or_not<4>(c, A, s, sd); break;
+        case 16: launch_sweep_b<1>(c, A, s, sd, trans); break;
+        case 32: launch_sweep_b<2>(c, A, s, sd, trans); break;
+        case 48: launch_sweep_b<3>(c, A, s, sd, trans); break;
+        default: launch_sweep_b<4>(c, A, s, sd, trans); break;
     }
+    c->cur_block = blk;
 }
 
 }  // namespace ials
