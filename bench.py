@@ -9,10 +9,11 @@ Inputs are resident in HBM before the timed region starts.
 value = nnz*b per second = 2 |S| d / (seconds per epoch): every epoch touches
 each observation once per block and side with b coordinates.
 
-Prints ONE JSON line.  The roofline object covers the dominant kernel, timed
-live with HIP events on the library's stream during the timed region; the CPU
-baseline is the FP64 oracle timed on this host over one full epoch of the same
-workload.
+The timed region replays the captured epoch graph K times.  The roofline
+object covers the dominant kernel, timed with HIP events on the library's
+stream over K more epochs launched kernel by kernel; the CPU baseline is the
+FP64 oracle timed on this host over one full epoch of the same workload.
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -36,18 +37,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def rows_work(lengths, b):
-    """Algorithmic FLOPs and bytes of one row-kernel launch: rows of <= SEG_LEN observations are
-    accumulated, solved, updated and patched; longer rows are only solved and updated there."""
+def rows_work(lengths, b, trans_fraction):
+    """Algorithmic FLOPs and bytes of one row-kernel launch.  Rows of <= SEG_LEN observations are
+    accumulated there (per observation: rank-1 Hessian update 2 b^2, gradient 2 b, prediction
+    dot product 2 b, plus 2 b more when the pass moves the cache to a new block); every row is
+    solved (Cholesky b^3/3 + two triangular solves 2 b^2) and updated.  trans_fraction is the
+    share of launches that move the cache."""
     import numpy as np
     lengths = np.asarray(lengths, np.int64)
-    short = lengths[lengths <= SEG_LEN]
-    nnz_s = int(short.sum())
+    nnz_s = int(lengths[lengths <= SEG_LEN].sum())
     n = lengths.size
-    flops = 2.0 * b * b * nnz_s + 2.0 * b * nnz_s + 2.0 * b * nnz_s + n * (b ** 3 / 3.0 + 2.0 * b * b)
-    # bytes: per observation gather b floats + index + yhat read, again gather + index + yhat write in the patch;
-    # per row: dense term b floats read, b floats of x read and written
-    bytes_ = nnz_s * (2 * (4 * b + 4) + 8) + n * (3 * 4 * b)
+    per_obs_flops = 2.0 * b * b + 4.0 * b + trans_fraction * 2.0 * b
+    flops = per_obs_flops * nnz_s + n * (b ** 3 / 3.0 + 2.0 * b * b)
+    # bytes: per observation the partner's block (4 b), its id, the cache entry, and for a moving
+    # pass the partner's old block and the cache write; per row the dense term and the row's block
+    per_obs_bytes = 4 * b + 4 + 4 + trans_fraction * (4 * b + 4)
+    bytes_ = nnz_s * per_obs_bytes + n * (4 * b + 2 * 4 * b + trans_fraction * 4 * b)
     return flops, bytes_
 
 
@@ -58,6 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ml20m_like")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of the sweep is "
@@ -76,7 +82,7 @@ def main():
     p = synth.make_problem(args.workload)
     log(f"[bench] generated in {time.time() - t0:.1f}s; building the index on the GPU")
     torch.cuda.set_device(0)
-    tr = Trainer(p)
+    tr = Trainer(p, graph=not args.no_graph)
     torch.cuda.synchronize()
     st = tr.stats()
     log(f"[bench] index built: long rows user {st['long_rows_user']} item {st['long_rows_item']}, "
@@ -87,16 +93,25 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup epoch {w + 1}/{args.warmup} done")
 
-    binding.ials_profile_enable(tr.ctx, True)
+    # timed region: K epochs replayed from the captured epoch graph (launch by launch with --no-graph)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
         tr.epoch(1)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    log(f"[bench] timed {args.steps} epochs in {t_total:.4f}s ({'graph' if not args.no_graph else 'eager'})")
+    # per-kernel times: the same K epochs launch by launch with HIP events around every kernel
+    binding.ials_profile_enable(tr.ctx, True)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter()
+    for s in range(args.steps):
+        tr.epoch(1)
+    torch.cuda.synchronize()
+    t_prof = time.perf_counter() - t_p
     prof = binding.ials_profile_read(tr.ctx)
     binding.ials_profile_enable(tr.ctx, False)
-    log(f"[bench] timed {args.steps} epochs in {t_total:.4f}s")
+    log(f"[bench] profiled {args.steps} epochs in {t_prof:.4f}s")
 
     L, parts = tr.loss()
     epoch_s = t_total / args.steps
@@ -109,12 +124,17 @@ def main():
     kern = {}
     for name, (ms, cnt) in prof.items():
         kern[name] = {"ms_per_epoch": ms / args.steps, "launches": cnt, "avg_ms": ms / max(cnt, 1)}
-    dom = max(("rows_user", "rows_item"), key=lambda k: kern.get(k, {"ms_per_epoch": 0})["ms_per_epoch"])
-    flops, bytes_ = rows_work(lu if dom == "rows_user" else li, p.block)
+    # dominant kernel: the row-kernel family with the most time per epoch
+    dom = max(("rows_user", "rows_user_move", "rows_item"),
+              key=lambda k: kern.get(k, {"ms_per_epoch": 0})["ms_per_epoch"])
+    flops, bytes_ = rows_work(li if dom == "rows_item" else lu, p.block, 1.0 if dom.endswith("_move") else 0.0)
     avg_s = kern[dom]["avg_ms"] / 1e3
     achieved = flops / avg_s / 1e12
     roofline = {
-        "kernel": f"k_sweep_rows ({dom.split('_')[1]} pass): gather + MFMA Hessian + Cholesky + update + yhat patch",
+        "kernel": {"rows_user": "k_sweep_rows<4,true,false,true> (user pass)",
+                   "rows_user_move": "k_sweep_rows<4,true,true,true> (user pass that moves the prediction cache)",
+                   "rows_item": "k_sweep_rows<4,true,false,false> (item pass)"}[dom]
+                  + ": gather + MFMA Hessian + blocked Cholesky + update",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
@@ -143,7 +163,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.num_users} users x {wl.num_items} items, {wl.nnz} observations "
                                f"(y=alpha=1), d={wl.dim}, b={wl.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
                    "epoch_s": epoch_s, "parallelism": "single GPU"},
-        "epoch_s": epoch_s, "loss_after": L,
+        "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern,
     }
     tr.close()

@@ -61,6 +61,13 @@ typedef enum { IALS_MEM_HOST = 0, IALS_MEM_DEVICE = 1 } ials_memkind;
  *       cores with float32 accumulation; gradients, solves and updates stay float32. */
 typedef enum { IALS_PREC_FP32 = 0, IALS_PREC_BF16 = 1 } ials_precision;
 
+/* IALS_FLAG_GRAPH: ials_epoch captures the launches of one epoch into a HIP graph
+ * on its first call and replays the graph afterwards (an epoch always runs the
+ * same launch sequence).  The context's stream must not be the NULL stream; if it
+ * is, ials_create makes a private stream for the context.  While profiling is on
+ * (ials_profile_enable) epochs run launch by launch. */
+enum { IALS_FLAG_GRAPH = 1u };
+
 typedef struct {
     int32_t num_users;          /* U >= 1 */
     int32_t num_items;          /* I >= 1 */
@@ -72,7 +79,7 @@ typedef struct {
     float chol_fallback_ratio;  /* tau: a row whose float32 Cholesky pivots satisfy
                                    min L_kk^2 < tau * max L_kk^2 (or any pivot <= 0)
                                    is refactored in float64; <= 0 selects 1e-6 */
-    uint32_t flags;             /* reserved, must be 0 */
+    uint32_t flags;             /* IALS_FLAG_* bits */
     uint32_t reserved;
     uint64_t hbm_budget;        /* upper bound on library-owned device bytes; 0 = no bound */
 } ials_config;
@@ -182,6 +189,8 @@ typedef enum {
     IALS_K_PATCH_USER = 11,   /* yhat patch of long-row segments */
     IALS_K_PATCH_ITEM = 12,
     IALS_K_LOSS = 13,
+    IALS_K_ROWS_USER_MOVE = 14, /* a row pass that also moves the prediction cache to its block */
+    IALS_K_ROWS_ITEM_MOVE = 15,
     IALS_K_NUM = 16
 } ials_kernel;
 

@@ -17,7 +17,7 @@ class Trainer:
     """Owns device copies of W, H (torch tensors) and one libials context."""
 
     def __init__(self, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
-                 stream=None, device: str = "cuda", hbm_budget: int = 0):
+                 stream=None, device: str = "cuda", hbm_budget: int = 0, graph: bool = False):
         import numpy as np
         import torch
 
@@ -25,9 +25,12 @@ class Trainer:
         self.problem = problem
         self.W = torch.from_numpy(np.ascontiguousarray(problem.W0)).to(device)
         self.H = torch.from_numpy(np.ascontiguousarray(problem.H0)).to(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if stream is None:
+            stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+        self.stream = stream
         cfg = binding.make_config(problem.num_users, problem.num_items, problem.dim, problem.block,
-                                  problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget)
+                                  problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget,
+                                  binding.IALS_FLAG_GRAPH if graph else 0)
         u = np.ascontiguousarray(problem.user, np.int32)
         i = np.ascontiguousarray(problem.item, np.int32)
         y = None if problem.y is None else np.ascontiguousarray(problem.y, np.float32)
@@ -39,6 +42,9 @@ class Trainer:
 
     def epoch(self, n: int = 1):
         binding.ials_epoch(self.ctx, n)
+
+    def synchronize(self):
+        self.stream.synchronize()
 
     def block_sweep(self, side: int, block: int):
         binding.ials_block_sweep(self.ctx, side, block)

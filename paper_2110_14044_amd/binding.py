@@ -32,6 +32,7 @@ IALS_MEM_HOST = 0
 IALS_MEM_DEVICE = 1
 IALS_PREC_FP32 = 0
 IALS_PREC_BF16 = 1
+IALS_FLAG_GRAPH = 1
 
 _STATUS_NAMES = {0: "IALS_OK", -1: "IALS_E_INVALID", -2: "IALS_E_NOMEM", -3: "IALS_E_HIP",
                  -4: "IALS_E_NOT_SPD", -5: "IALS_E_BUSY", -6: "IALS_E_STATE"}
@@ -198,7 +199,7 @@ def ials_set_stream(ctx: int, stream) -> None:
 
 KERNEL_NAMES = ["predict", "gram_user", "gram_item", "dense_user", "dense_item", "seg_user", "seg_item",
                 "rows_user", "rows_item", "fallback_user", "fallback_item", "patch_user", "patch_item", "loss",
-                "k14", "k15"]
+                "rows_user_move", "rows_item_move"]
 
 
 def ials_profile_enable(ctx: int, enable: bool) -> None:
@@ -222,8 +223,8 @@ def ials_version() -> str:
 
 
 def make_config(num_users, num_items, dim, block, alpha0, lam, precision=IALS_PREC_FP32,
-                chol_fallback_ratio=0.0, hbm_budget=0) -> ials_config:
-    return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, 0, 0,
+                chol_fallback_ratio=0.0, hbm_budget=0, flags=0) -> ials_config:
+    return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, flags, 0,
                        hbm_budget)
 
 

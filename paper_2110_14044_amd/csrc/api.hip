@@ -16,8 +16,10 @@ thread_local std::string g_create_error;
 void free_ctx(ials_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->epoch_exec) (void)hipGraphExecDestroy(c->epoch_exec);
     for (void* p : c->owned) (void)hipFree(p);
     for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -133,8 +135,8 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
         g_create_error = "only IALS_PREC_FP32 is available in this build";
         return IALS_E_INVALID;
     }
-    if (cfg->flags != 0) {
-        g_create_error = "flags must be 0";
+    if ((cfg->flags & ~(uint32_t)IALS_FLAG_GRAPH) != 0) {
+        g_create_error = "unknown flag bits";
         return IALS_E_INVALID;
     }
     if (S->nnz < 0 || S->nnz > (int64_t)INT32_MAX || (S->nnz > 0 && (!S->user || !S->item)) ||
@@ -168,6 +170,11 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->W = W;
     c->H = H;
     c->budget = cfg->hbm_budget;
+    c->flags = cfg->flags;
+    if ((c->flags & IALS_FLAG_GRAPH) && c->stream == nullptr) {
+        TRY_HIP_CREATE(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
     TRY_HIP_CREATE(hipGetDevice(&c->device));
     int ncu = 0;
     TRY_HIP_CREATE(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
@@ -329,20 +336,54 @@ ials_status ials_refresh_predictions(ials_ctx* c) {
     return IALS_OK;
 }
 
+// The launches of one epoch of Alg. 3.
+ials_status launch_epoch(ials_ctx* c) {
+    const int32_t nblocks = (c->d + c->b - 1) / c->b;
+    {
+        ials::ProfScope ps(c, IALS_K_PREDICT);
+        ials::launch_predict(c, 0, false, c->yhat);
+        c->cur_block = 0;
+    }
+    for (int32_t blk = 0; blk < nblocks; ++blk) {
+        ials_status s = run_pass(c, IALS_SIDE_USER, blk);
+        if (s != IALS_OK) return s;
+        s = run_pass(c, IALS_SIDE_ITEM, blk);
+        if (s != IALS_OK) return s;
+    }
+    return IALS_OK;
+}
+
 ials_status ials_epoch(ials_ctx* c, int32_t n_epochs) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
     if (n_epochs < 0) return fail(c, IALS_E_INVALID, "n_epochs < 0");
+    const bool graph = (c->flags & IALS_FLAG_GRAPH) && !c->prof;
+    if (graph && n_epochs > 0 && !c->epoch_exec) {
+        const int64_t passes0 = c->passes;
+        IALS_HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        ials_status s = launch_epoch(c);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (s != IALS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(c, IALS_E_HIP, std::string("epoch capture failed: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->epoch_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->epoch_exec = nullptr;
+            return fail(c, IALS_E_HIP, std::string("epoch graph instantiation failed: ") + hipGetErrorString(e));
+        }
+        c->passes = passes0;  // nothing ran during the capture
+    }
     const int32_t nblocks = (c->d + c->b - 1) / c->b;
     for (int32_t t = 0; t < n_epochs; ++t) {
-        {
-            ials::ProfScope ps(c, IALS_K_PREDICT);
-            ials::launch_predict(c, 0, false, c->yhat);
-            c->cur_block = 0;
-        }
-        for (int32_t blk = 0; blk < nblocks; ++blk) {
-            ials_status s = run_pass(c, IALS_SIDE_USER, blk);
-            if (s != IALS_OK) return s;
-            s = run_pass(c, IALS_SIDE_ITEM, blk);
+        if (graph) {
+            IALS_HIP_TRY(c, hipGraphLaunch(c->epoch_exec, c->stream));
+            c->cur_block = nblocks - 1;
+            c->passes += 2 * nblocks;
+        } else {
+            ials_status s = launch_epoch(c);
             if (s != IALS_OK) return s;
         }
     }

@@ -82,6 +82,9 @@ struct ials_ctx {
     size_t loss_part_len = 0;
     double* gram64 = nullptr;    // [2 * d * d] float64 Gramians for the loss
     double* loss_out = nullptr;  // [4]
+    uint32_t flags = 0;
+    bool own_stream = false;
+    hipGraphExec_t epoch_exec = nullptr;  // captured epoch (IALS_FLAG_GRAPH)
     uint64_t device_bytes = 0;
     uint64_t budget = 0;
     int64_t passes = 0;

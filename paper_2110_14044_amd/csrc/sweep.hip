@@ -79,10 +79,13 @@ __device__ inline void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-// Next item from a work queue shared by all wavefronts.
+// Next item from a work queue shared by all wavefronts.  The first active lane
+// takes the item and broadcasts it, so the protocol holds for any exec mask.
 __device__ inline int queue_next(int32_t* cursor, int lane) {
+    const unsigned long long active = __ballot(1);
+    const int leader = __ffsll((long long)active) - 1;
     int it = 0;
-    if (lane == 0) it = atomicAdd(cursor, 1);
+    if (lane == leader) it = atomicAdd(cursor, 1);
     return __builtin_amdgcn_readfirstlane(it);
 }
 __device__ inline float sum16(float s) {
@@ -279,7 +282,7 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
     dtiles[e] = Dmat[colmap<NT, FULL>(16 * ti + 4 * (lq >> 4) + j) * B + colmap<NT, FULL>(16 * tj + (lq & 15))];
 }
 
-template <int NT, bool FULL, bool TRANS>
+template <int NT, bool FULL, bool TRANS, bool STATIC>
 __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
@@ -287,14 +290,14 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
     float* pan = lds_all + wave * rows_lds_floats_per_wave<NT>();
     const int my_col = colmap<NT, FULL>(lane < B ? lane : 0);
 
-    // rows_batch == 0: rows are dealt round-robin in the length order (sides whose rows
-    // are all short); otherwise each wavefront takes the next row from a shared queue.
-    int it = A.rows_batch ? 0 : blockIdx.x * 4 + wave;
+    // STATIC: rows are dealt round-robin in the length order (sides whose rows are all
+    // short); otherwise each wavefront takes the next row from a shared queue.
+    int it = STATIC ? blockIdx.x * 4 + wave : 0;
     for (;;) {
-        if (A.rows_batch) it = queue_next(&A.cursors[CUR_ROWS], lane);
+        if constexpr (!STATIC) it = queue_next(&A.cursors[CUR_ROWS], lane);
         if (it >= A.nrows) break;
         const int r = A.order[it];
-        if (!A.rows_batch) it += gridDim.x * 4;
+        if constexpr (STATIC) it += gridDim.x * 4;
         const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
         floatx4 acc[NTL];
 #pragma unroll
@@ -420,7 +423,9 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
             pmin = fminf(pmin, __shfl_xor(pmin, m));
             pmax = fmaxf(pmax, __shfl_xor(pmax, m));
         }
-        const bool bad = !(pmin > 0.f) || (pmin < A.tau * pmax);
+        // identical in every lane after the reductions; made explicitly uniform so the
+        // row loop stays a uniform loop (its queue step needs the whole wave)
+        const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < A.tau * pmax)) ? 1 : 0);
         if (bad) {
             if (lane == 0) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
@@ -570,20 +575,25 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
         hipLaunchKernelGGL((k_make_dtiles<NT, FULL>), dim3((ntiles<NT>() * 256 + 255) / 256), dim3(256), 0, st, args.Dmat,
                            args.dtiles);
         {
-            ProfScope ps(c, IALS_K_ROWS_USER + sd);
-            // static dealing: exactly the blocks that are resident at once
-            static int resident = 0;
-            if (resident == 0) {
-                int nb = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS>, 256, lds) !=
-                        hipSuccess ||
-                    nb < 1)
-                    nb = 2;
-                resident = nb;
+            ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
+            if (args.rows_batch == 0) {
+                // static dealing: exactly the blocks that are resident at once
+                static int resident = 0;
+                if (resident == 0) {
+                    int nb = 0;
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS, true>, 256,
+                                                                     lds) != hipSuccess ||
+                        nb < 1)
+                        nb = 2;
+                    resident = nb;
+                }
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true>),
+                                   dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
+                                   dim3(256), lds, st, args);
+            } else {
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, false>),
+                                   dim3(std::min<unsigned>(max_blocks, (s.nrows + 3) / 4)), dim3(256), lds, st, args);
             }
-            const unsigned rows_blocks = args.rows_batch ? max_blocks : (unsigned)(c->num_cu * resident);
-            hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS>),
-                               dim3(std::min<unsigned>(rows_blocks, (s.nrows + 3) / 4)), dim3(256), lds, st, args);
         }
         ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
         hipLaunchKernelGGL((k_sweep_fallback<NT>), dim3((unsigned)c->num_cu), dim3(256), 0, st, args);

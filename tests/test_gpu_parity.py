@@ -181,3 +181,23 @@ def test_forced_fallback_on_long_rows_full_blocks():
     p = synth.small_problem(51, 3000, 120, 60_000, 64, 32, labels=True, zipf_s=0.8, std=0.1)
     st = _epoch_check(p, 1, 1e-4, 1e-6, chol_fallback_ratio=1.0)
     assert st["fallback_rows"] == (p.num_users + p.num_items) * 2 and st["segments_item"] > 0
+
+
+def test_graph_epochs_match_eager_bitwise():
+    """The captured epoch graph, replayed several times with eager work and
+    synchronisations in between, gives the eager epochs' results bit for bit."""
+    p = synth.small_problem(80, 3000, 150, 40_000, 64, 32, zipf_s=0.8, std=0.1, labels=True)
+    eager = gpu_trainer(p)
+    graph = gpu_trainer(p, graph=True)
+    for t in range(3):
+        eager.epoch(1)
+        graph.epoch(1)
+        graph.synchronize()
+        L_e, _ = eager.loss()
+        L_g, _ = graph.loss()  # eager loss kernels on the graph context between replays
+        assert np.array_equal(host(eager.W), host(graph.W)), t
+        assert np.array_equal(host(eager.H), host(graph.H)), t
+        assert L_e == L_g
+        assert np.array_equal(eager.predictions(), graph.predictions())
+    eager.close()
+    graph.close()
