@@ -56,6 +56,21 @@ def rows_work(lengths, b, trans_fraction):
     return flops, bytes_
 
 
+def measured_traffic(kernel_family):
+    """HBM bytes per launch from the committed counter summary, or None if the sweep kernels
+    changed since the counters were taken (or the summary is for another kernel)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_sweep_rows_ml20m_like.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
+    src = os.path.join(ROOT, "paper_2110_14044_amd", "csrc", "sweep.hip")
+    if kv.get("kernel") != kernel_family or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get(
+            "sweep_hip_sha256"):
+        return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +79,19 @@ def main():
     ap.add_argument("--workload", default="ml20m_like")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 256 * 2 ** 20
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of the sweep is "
               "a design in DESIGN.md, not built.", file=sys.stderr)
@@ -136,7 +163,7 @@ def main():
                    "rows_item": "k_sweep_rows<4,true,false,false> (item pass)"}[dom]
                   + ": gather + MFMA Hessian + blocked Cholesky + update",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None,
+        "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(dom),
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
         "avg_launch_ms": kern[dom]["avg_ms"],
         "algorithmic_GBps": round(bytes_ / avg_s / 1e9, 1),
