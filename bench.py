@@ -31,6 +31,7 @@ METRIC = "epoch sec + nnz·b/s; p99 fold-in ms vs plain FP32 iALS++ at matched l
 SEG_LEN = 1024          # rows longer than this are accumulated by the segment kernel
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0       # GB/s
+SERVE_RATES = (1000, 5000, 20000)  # open-loop Poisson arrival rates, requests per second
 
 
 def log(*a):
@@ -71,6 +72,79 @@ def measured_traffic(kernel_family):
     return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
 
 
+def _open_loop(srv, reqs, arrivals, d):
+    """Submit request k at its scheduled arrival time (retrying while the server answers BUSY)
+    and poll continuously; latency = host time the result is seen - scheduled arrival."""
+    import numpy as np
+    from paper_2110_14044_amd import binding
+    n = len(reqs)
+    lat = np.zeros(n)
+    hit_busy = np.zeros(n, bool)
+    tags = np.zeros(1024, np.uint64)
+    rows = np.zeros((1024, d), np.float32)
+    st = np.zeros(1024, np.int32)
+    i = got = 0
+    h = srv.srv
+    t0 = time.perf_counter()
+    while got < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals[i] <= now:
+            if binding.ials_server_submit(h, reqs[i], None, i) != binding.IALS_OK:
+                hit_busy[i] = True
+                break
+            i += 1
+        k = binding.ials_server_poll_into(h, 0, tags, rows, st)
+        if k:
+            t = time.perf_counter() - t0
+            idx = tags[:k].astype(np.int64)
+            lat[idx] = t - arrivals[idx]
+            got += k
+            if np.any(st[:k] != 0) or not np.all(np.isfinite(rows[:k])):
+                raise RuntimeError("a fold-in result failed")
+    return lat, time.perf_counter() - t0, int(hit_busy.sum())
+
+
+def serving_bench(n_req, warm, rates):
+    """Fold-in serving: item table 41,000 x 256 (seeded N(0, 0.1/sqrt(d))), b=64, alpha0=0.1,
+    lambda=0.05, 3 sweeps per request, request lengths lognormal(3.5, 1.2) clipped to [1, 2000]
+    over Zipf(0.9) items, open-loop Poisson arrivals.  Two modes on the same kernel:
+    continuous batching (1024 slots, 4 streams) and the per-request path (1 slot, 1 stream:
+    every request is its own launch, one at a time)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2110_14044_amd import FoldinServer
+    H = torch.from_numpy(synth.serving_table(2024)).cuda()
+    ptr, items = synth.serving_requests(2025, n_req + warm)
+    reqs = [np.ascontiguousarray(items[ptr[r]:ptr[r + 1]]) for r in range(n_req + warm)]
+    out = {"workload": f"fold-in: H 41000 x 256 fp32 resident, b=64, 3 sweeps, lengths lognormal(3.5,1.2) "
+                       f"clipped [1,2000] (mean {float(np.diff(ptr).mean()):.1f}), Zipf(0.9) items; "
+                       f"{n_req} requests per rate after {warm} warm-up"}
+    for mode, kw in (("batched", dict(max_slots=1024, streams=4)), ("per_request", dict(max_slots=1, streams=1))):
+        srv = FoldinServer(H, 64, 0.1, 0.05, passes=3, **kw)
+        res = {}
+        for rate in rates:
+            arr = synth.poisson_arrivals(3000 + rate, n_req + warm, float(rate))
+            b0 = srv.stats()["batches"]
+            lat, wall, busy = _open_loop(srv, reqs, arr, 256)
+            m = lat[warm:] * 1e3
+            done = arr[warm:] + lat[warm:]
+            res[str(rate)] = {"p50_ms": round(float(np.percentile(m, 50)), 4),
+                              "p99_ms": round(float(np.percentile(m, 99)), 4),
+                              "mean_ms": round(float(m.mean()), 4),
+                              "solves_per_s": round(n_req / float(done.max() - arr[warm]), 1),
+                              "busy_retried": busy, "batches": srv.stats()["batches"] - b0}
+            log(f"[bench] serving {mode} {rate}/s: p50 {res[str(rate)]['p50_ms']:.3f} ms "
+                f"p99 {res[str(rate)]['p99_ms']:.3f} ms, {res[str(rate)]['solves_per_s']:.0f} solves/s, "
+                f"{res[str(rate)]['batches']} batches, wall {wall:.1f}s")
+        st = srv.stats()
+        res["max_batch"] = st["max_batch"]
+        srv.close()
+        out[mode] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +153,10 @@ def main():
     ap.add_argument("--workload", default="ml20m_like")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
+    ap.add_argument("--serving", choices=("on", "off", "only"), default="on",
+                    help="fold-in serving measurement beside the training epochs")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-warmup", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -102,6 +180,10 @@ def main():
 
     import synth
     from paper_2110_14044_amd import Trainer, binding
+
+    if args.serving == "only":
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, SERVE_RATES)}))
+        return
 
     wl = synth.workload(args.workload)
     log(f"[bench] generating {wl.name}: {wl.num_users}x{wl.num_items}, {wl.nnz} obs, d={wl.dim} b={wl.block}")
@@ -183,6 +265,11 @@ def main():
                "sample": f"one full epoch of {wl.name} (from W0, H0; includes the per-epoch loss), "
                          f"{t_cpu:.2f} s", "epoch_s": t_cpu}
 
+    serving = None
+    if args.serving == "on":
+        tr.close()
+        serving = serving_bench(args.serve_requests, args.serve_warmup, SERVE_RATES)
+
     out = {
         "metric": METRIC, "value": value, "unit": "nnz·b/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": epoch_s * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -191,7 +278,7 @@ def main():
                                f"(y=alpha=1), d={wl.dim}, b={wl.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
                    "epoch_s": epoch_s, "parallelism": "single GPU"},
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
-        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern,
+        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "serving": serving,
     }
     tr.close()
     print(json.dumps(out))

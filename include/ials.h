@@ -104,6 +104,8 @@ typedef struct {
     int64_t fallback_rows;     /* rows refactored in float64 since create */
     int64_t passes;            /* block passes run since create */
     uint64_t device_bytes;     /* library-owned device memory */
+    int64_t foldin_requests;   /* rows folded in by ials_foldin since create */
+    int64_t foldin_float64;    /* of those, rows redone in float64 */
 } ials_stats;
 
 /*
@@ -173,6 +175,33 @@ IALS_API ials_status ials_get_predictions(ials_ctx* ctx, float* out_host);
 /* Counters and sizes.  Synchronising. */
 IALS_API ials_status ials_get_stats(ials_ctx* ctx, ials_stats* out);
 
+/*
+ * Fold-in (sec. 4, Alg. 3 for a single new row with the item side fixed; eq. 3
+ * is its limit): for each request r, a new user who observed the items
+ * items[req_ptr[r] .. req_ptr[r+1]) (labels y, or all ones; weights 1), start
+ * from w = 0 and run `passes` sweeps over the blocks in ascending order, each a
+ * block Newton step against the context's current H and G = H^T H (eq. 8-9 with
+ * the predictions of this row only).  The result row r is written to
+ * W_out[r*d .. r*d+d).
+ *   req_ptr  HOST array of n_req+1 non-decreasing offsets, req_ptr[0] = 0;
+ *   items    DEVICE int32 [req_ptr[n_req]], ids in [0, I);
+ *   y        DEVICE float [req_ptr[n_req]] labels, or NULL for all ones;
+ *   W_out    DEVICE float [n_req * d], caller-owned.
+ * Every request's block Hessians are factored once (H does not change during a
+ * fold-in) in float32; a request whose pivots fail the chol_fallback_ratio test
+ * is redone entirely in float64.  Requests are independent: a request's result
+ * does not depend on the other requests of the call.  G is re-formed when a
+ * training pass has run since the previous fold-in (changes made to H outside
+ * the library after that are not seen).  Runs on the context's stream in
+ * chunks that fit the fold-in scratch allocated by ials_create; returns
+ * IALS_E_INVALID for bad offsets, an item id out of range (detected on the
+ * device; the call then leaves W_out undefined) or a request longer than the
+ * scratch, IALS_E_NOT_SPD if a request failed even in float64 (its row is NaN).
+ * Synchronising.
+ */
+IALS_API ials_status ials_foldin(ials_ctx* ctx, int32_t n_req, const int64_t* req_ptr, const int32_t* items,
+                                 const float* y, int32_t passes, float* W_out);
+
 /* Kernel families timed by the profiling hooks below (index into the arrays). */
 typedef enum {
     IALS_K_PREDICT = 0,       /* yhat recompute at the start of an epoch (eq. 1) */
@@ -210,6 +239,85 @@ IALS_API ials_status ials_set_stream(ials_ctx* ctx, void* hip_stream);
 
 /* Text of the last error on ctx (or of the last failed ials_create when ctx is NULL). */
 IALS_API const char* ials_last_error(const ials_ctx* ctx);
+
+/*
+ * Fold-in server: continuous batching of fold-in requests (the fold-in above)
+ * against a resident item table.  The server keeps G = H^T H on the device,
+ * admits each request into a slot and a region of its device arena (the HBM
+ * budget), and a worker thread launches everything admitted as one batch on
+ * the next free stream while earlier batches are still running, so requests
+ * that arrive while others are on the GPU start as soon as a stream is free.
+ * Each request runs in its own workgroup with the same arithmetic whatever the
+ * batch holds: a result is bitwise the same alone or in any mix.
+ */
+typedef struct ials_server ials_server;
+
+typedef struct {
+    int32_t num_items;          /* I >= 1, rows of H */
+    int32_t dim;                /* d >= 1 */
+    int32_t block;              /* b, 1 <= b <= min(d, 64) */
+    float alpha0;               /* >= 0 */
+    float lambda;               /* > 0 */
+    int32_t precision;          /* ials_precision (IALS_PREC_FP32) */
+    int32_t passes;             /* sweeps per request, 0..1000 */
+    int32_t max_slots;          /* requests admitted at once (queued, running or unpolled), >= 1 */
+    int32_t streams;            /* batches in flight at once, 1..8; 0 selects 4 */
+    float chol_fallback_ratio;  /* tau as in ials_config; <= 0 selects 1e-6 */
+    uint64_t hbm_budget;        /* bytes of the device arena for request state; 0 selects 64 MiB */
+} ials_server_config;
+
+typedef struct {
+    int64_t submitted;          /* admitted requests */
+    int64_t rejected_busy;      /* submissions answered IALS_E_BUSY */
+    int64_t completed;          /* requests whose batch finished */
+    int64_t polled;             /* results handed out by ials_server_poll */
+    int64_t batches;            /* batches launched */
+    int64_t max_batch;          /* largest batch */
+    int64_t float64_requests;   /* polled results that were redone in float64 */
+    int64_t not_spd_requests;   /* polled results that failed in float64 */
+    int32_t admitted;           /* requests holding a slot now */
+    int32_t in_flight;          /* batches on the device now */
+    uint64_t arena_bytes;       /* hbm_budget */
+    uint64_t bytes_in_use;      /* arena bytes held by admitted requests */
+    uint64_t bytes_peak;
+} ials_server_stats;
+
+/* Create a server on the current device.  H is a DEVICE float [I x d] table,
+ * BORROWED: it must stay alive and unchanged until ials_server_destroy.
+ * Allocates the arena (hbm_budget bytes of device memory and as much pinned
+ * host memory), G, one stream per batch in flight, and starts the worker
+ * thread.  Synchronising.  On failure *out is NULL and
+ * ials_server_last_error(NULL) describes the error. */
+IALS_API ials_status ials_server_create(const ials_server_config* cfg, const float* H, ials_server** out);
+
+/* Submit one request: n >= 0 HOST item ids (and HOST labels y, or NULL for ones),
+ * copied before the call returns; tag is returned with the result.  Returns
+ * IALS_OK if admitted, IALS_E_BUSY if every slot is taken or the arena has no
+ * room for it now (nothing was queued: retry after polling), IALS_E_INVALID
+ * for an id out of range or a request larger than the whole arena, IALS_E_STATE
+ * once the worker has failed.  Thread-safe; never blocks on the device. */
+IALS_API ials_status ials_server_submit(ials_server* srv, int32_t n, const int32_t* items, const float* y,
+                                        uint64_t tag);
+
+/* Hand out up to max finished results: tags[k], the row w_out[k*d .. k*d+d)
+ * (HOST) and status[k] (nullable; 0 = float32 path, 1 = redone in float64,
+ * 2 = not SPD in float64: row is NaN).  Waits up to wait_us microseconds for a
+ * first result when none is ready.  *n_done receives the count.  Frees the
+ * results' slots and arena regions.  Thread-safe.  Returns IALS_E_HIP once a
+ * device error has stopped the worker (results finished before it are still
+ * handed out). */
+IALS_API ials_status ials_server_poll(ials_server* srv, int32_t max, int32_t wait_us, uint64_t* tags, float* w_out,
+                                      int32_t* status, int32_t* n_done);
+
+/* Counters of the server.  Thread-safe. */
+IALS_API ials_status ials_server_stats_get(ials_server* srv, ials_server_stats* out);
+
+/* Stop the worker (requests not yet launched are dropped, running batches are
+ * waited for) and release everything the server allocated.  Never frees H. */
+IALS_API ials_status ials_server_destroy(ials_server* srv);
+
+/* Text of the last error of srv (or of the last failed ials_server_create when srv is NULL). */
+IALS_API const char* ials_server_last_error(const ials_server* srv);
 
 /* Library version string. */
 IALS_API const char* ials_version(void);

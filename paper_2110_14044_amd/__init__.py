@@ -10,7 +10,7 @@ from __future__ import annotations
 from . import binding
 from .binding import IalsError
 
-__all__ = ["binding", "IalsError", "Trainer"]
+__all__ = ["binding", "IalsError", "Trainer", "FoldinServer"]
 
 
 class Trainer:
@@ -73,10 +73,64 @@ class Trainer:
     def stats(self):
         return binding.ials_get_stats(self.ctx)
 
+    def foldin(self, req_ptr, items, y=None, passes: int = 3):
+        """Fold in new users against the current H: req_ptr (host int64 offsets), items and
+        y host arrays or device tensors; returns a (n_req, d) float32 device tensor."""
+        import numpy as np
+        import torch
+        dev = self.W.device
+        it = items if isinstance(items, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(items, np.int32))
+        it = it.to(dev)
+        yv = None
+        if y is not None:
+            yv = y if isinstance(y, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(y, np.float32))
+            yv = yv.to(dev)
+        req_ptr = np.ascontiguousarray(req_ptr, np.int64)
+        out = torch.empty((req_ptr.size - 1, self.problem.dim), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        binding.ials_foldin(self.ctx, req_ptr, it, yv, passes, out)
+        return out
+
     def close(self):
         if getattr(self, "ctx", None):
             binding.ials_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FoldinServer:
+    """Continuous-batching fold-in server around a device item table H (torch tensor, kept alive here)."""
+
+    def __init__(self, H, block: int, alpha0: float, lam: float, passes: int = 3, max_slots: int = 1024,
+                 streams: int = 4, hbm_budget: int = 0, chol_fallback_ratio: float = 0.0):
+        import torch
+        binding.load()
+        self.H = H.contiguous()
+        self.d = int(self.H.shape[1])
+        cfg = binding.make_server_config(int(self.H.shape[0]), self.d, block, alpha0, lam, passes, max_slots,
+                                         streams, hbm_budget, chol_fallback_ratio)
+        torch.cuda.synchronize()
+        self.srv = binding.ials_server_create(cfg, self.H)
+
+    def submit(self, items, y=None, tag: int = 0) -> bool:
+        """True if admitted, False if the server answered IALS_E_BUSY."""
+        return binding.ials_server_submit(self.srv, items, y, tag) == binding.IALS_OK
+
+    def poll(self, max_n: int = 256, wait_us: int = 0):
+        return binding.ials_server_poll(self.srv, max_n, wait_us, self.d)
+
+    def stats(self):
+        return binding.ials_server_stats_get(self.srv)
+
+    def close(self):
+        if getattr(self, "srv", None):
+            binding.ials_server_destroy(self.srv)
+            self.srv = None
 
     def __del__(self):
         try:

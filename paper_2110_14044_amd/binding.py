@@ -55,7 +55,25 @@ class ials_stats(C.Structure):
                 ("dim", C.c_int32), ("block", C.c_int32), ("padded_block", C.c_int32),
                 ("long_rows_user", C.c_int32), ("long_rows_item", C.c_int32),
                 ("segments_user", C.c_int64), ("segments_item", C.c_int64),
-                ("fallback_rows", C.c_int64), ("passes", C.c_int64), ("device_bytes", C.c_uint64)]
+                ("fallback_rows", C.c_int64), ("passes", C.c_int64), ("device_bytes", C.c_uint64),
+                ("foldin_requests", C.c_int64), ("foldin_float64", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ials_server_config(C.Structure):
+    _fields_ = [("num_items", C.c_int32), ("dim", C.c_int32), ("block", C.c_int32), ("alpha0", C.c_float),
+                ("lambda_", C.c_float), ("precision", C.c_int32), ("passes", C.c_int32), ("max_slots", C.c_int32),
+                ("streams", C.c_int32), ("chol_fallback_ratio", C.c_float), ("hbm_budget", C.c_uint64)]
+
+
+class ials_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("rejected_busy", C.c_int64), ("completed", C.c_int64),
+                ("polled", C.c_int64), ("batches", C.c_int64), ("max_batch", C.c_int64),
+                ("float64_requests", C.c_int64), ("not_spd_requests", C.c_int64), ("admitted", C.c_int32),
+                ("in_flight", C.c_int32), ("arena_bytes", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("bytes_peak", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,8 +103,16 @@ _SIGS = {
     "ials_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ials_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ials_profile_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ials_foldin": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "ials_last_error": (C.c_char_p, [C.c_void_p]),
     "ials_version": (C.c_char_p, []),
+    "ials_server_create": (C.c_int, [C.POINTER(ials_server_config), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ials_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64]),
+    "ials_server_poll": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_int32)]),
+    "ials_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ials_server_stats)]),
+    "ials_server_destroy": (C.c_int, [C.c_void_p]),
+    "ials_server_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
 
@@ -113,6 +139,12 @@ def exported_symbols():
 def _check(st: int, ctx=None):
     if st != IALS_OK:
         msg = load().ials_last_error(ctx)
+        raise IalsError(st, msg.decode() if msg else "")
+
+
+def _check_srv(st: int, srv=None):
+    if st != IALS_OK:
+        msg = load().ials_server_last_error(srv)
         raise IalsError(st, msg.decode() if msg else "")
 
 
@@ -211,6 +243,70 @@ def ials_profile_read(ctx: int) -> dict:
     cnt = np.zeros(16, np.int64)
     _check(load().ials_profile_read(ctx, ms.ctypes.data, cnt.ctypes.data), ctx)
     return {KERNEL_NAMES[k]: (float(ms[k]), int(cnt[k])) for k in range(16) if cnt[k] > 0}
+
+
+def ials_foldin(ctx: int, req_ptr: np.ndarray, items, y, passes: int, W_out) -> None:
+    """req_ptr: host int64 offsets; items / y / W_out: device tensors (y may be None)."""
+    req_ptr = np.ascontiguousarray(req_ptr, np.int64)
+    _check(load().ials_foldin(ctx, req_ptr.size - 1, req_ptr.ctypes.data, _ptr(items), _ptr(y), passes,
+                              _ptr(W_out)), ctx)
+
+
+def ials_server_create(cfg: ials_server_config, H) -> int:
+    out = C.c_void_p()
+    _check_srv(load().ials_server_create(C.byref(cfg), _ptr(H), C.byref(out)), None)
+    return out.value
+
+
+def ials_server_submit(srv: int, items: np.ndarray, y: Optional[np.ndarray], tag: int) -> int:
+    """Returns IALS_OK or IALS_E_BUSY; raises on any other status."""
+    items = np.ascontiguousarray(items, np.int32)
+    yv = None if y is None else np.ascontiguousarray(y, np.float32)
+    st = load().ials_server_submit(srv, items.size, items.ctypes.data, None if yv is None else yv.ctypes.data, tag)
+    if st not in (IALS_OK, IALS_E_BUSY):
+        _check_srv(st, srv)
+    return st
+
+
+def ials_server_poll(srv: int, max_n: int, wait_us: int, d: int):
+    """Returns (tags uint64[k], rows float32[k, d], status int32[k])."""
+    tags = np.zeros(max(max_n, 1), np.uint64)
+    rows = np.zeros((max(max_n, 1), d), np.float32)
+    status = np.zeros(max(max_n, 1), np.int32)
+    n = C.c_int32()
+    _check_srv(load().ials_server_poll(srv, max_n, wait_us, tags.ctypes.data, rows.ctypes.data, status.ctypes.data,
+                                       C.byref(n)), srv)
+    k = n.value
+    return tags[:k], rows[:k], status[:k]
+
+
+def ials_server_poll_into(srv: int, wait_us: int, tags: np.ndarray, rows: np.ndarray, status: np.ndarray) -> int:
+    """Poll into preallocated uint64[m], float32[m, d], int32[m] arrays; returns the count."""
+    n = C.c_int32()
+    _check_srv(load().ials_server_poll(srv, tags.size, wait_us, tags.ctypes.data, rows.ctypes.data,
+                                       status.ctypes.data, C.byref(n)), srv)
+    return n.value
+
+
+def ials_server_stats_get(srv: int) -> dict:
+    s = ials_server_stats()
+    _check_srv(load().ials_server_stats_get(srv, C.byref(s)), srv)
+    return s.as_dict()
+
+
+def ials_server_destroy(srv: int) -> None:
+    _check_srv(load().ials_server_destroy(srv), None)
+
+
+def ials_server_last_error(srv: Optional[int] = None) -> str:
+    m = load().ials_server_last_error(srv)
+    return m.decode() if m else ""
+
+
+def make_server_config(num_items, dim, block, alpha0, lam, passes=3, max_slots=1024, streams=4,
+                       hbm_budget=0, chol_fallback_ratio=0.0, precision=IALS_PREC_FP32) -> ials_server_config:
+    return ials_server_config(num_items, dim, block, alpha0, lam, precision, passes, max_slots, streams,
+                              chol_fallback_ratio, hbm_budget)
 
 
 def ials_last_error(ctx: Optional[int] = None) -> str:

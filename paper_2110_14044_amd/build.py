@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libials.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["csr.hip", "dense.hip", "sweep.hip", "api.hip"]
+SOURCES = ["csr.hip", "dense.hip", "sweep.hip", "foldin.hip", "serve.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [
@@ -21,7 +21,7 @@ COMMON = [
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
-    "-I", INCLUDE, "-I", CSRC,
+    "-I", INCLUDE, "-I", CSRC, "-pthread",
 ]
 
 
@@ -44,7 +44,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)

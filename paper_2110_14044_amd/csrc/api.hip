@@ -18,6 +18,7 @@ void free_ctx(ials_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->epoch_exec) (void)hipGraphExecDestroy(c->epoch_exec);
     for (void* p : c->owned) (void)hipFree(p);
+    for (void* p : c->owned_host) (void)hipHostFree(p);
     for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -263,6 +264,19 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     TRY_ALLOC(c, c->loss_part, sizeof(double) * c->loss_part_len);
     TRY_ALLOC(c, c->gram64, sizeof(double) * 2 * dd);
     TRY_ALLOC(c, c->loss_out, sizeof(double) * 4);
+    // fold-in: G = H^T H, counters, request scratch and pinned request descriptors
+    c->fold = ials::fold_shape(c->I, c->d, c->b);
+    TRY_ALLOC(c, c->fold_G, sizeof(float) * dd);
+    TRY_ALLOC(c, c->fold_cnt, sizeof(int32_t) * ials::FOLD_CNT_NUM);
+    c->fold_ws_cap = ((size_t)1 << 22) + (c->fold.gfac ? 64 * ials::fold_ws_floats(c->fold, 0) : 0);
+    TRY_ALLOC(c, c->fold_ws, sizeof(float) * c->fold_ws_cap);
+    c->fold_req_cap = 16384;
+    {
+        void* hp = nullptr;
+        TRY_HIP_CREATE(hipHostMalloc(&hp, sizeof(ials::FoldReq) * c->fold_req_cap, hipHostMallocMapped));
+        c->owned_host.push_back(hp);
+        c->fold_req = static_cast<ials::FoldReq*>(hp);
+    }
 
     c->cur_block = 0;
     ials::launch_predict(c, 0, false, c->yhat);
@@ -465,6 +479,8 @@ ials_status ials_get_stats(ials_ctx* c, ials_stats* o) {
     o->fallback_rows = cnt[ials::CNT_FALLBACK_ROWS];
     o->passes = c->passes;
     o->device_bytes = c->device_bytes;
+    o->foldin_requests = c->fold_requests;
+    o->foldin_float64 = c->fold_float64;
     return IALS_OK;
 }
 
@@ -502,6 +518,64 @@ ials_status ials_profile_read(ials_ctx* c, double* total_ms, int64_t* launches) 
         c->prof_ms[k] = 0.0;
         c->prof_count[k] = 0;
     }
+    return IALS_OK;
+}
+
+ials_status ials_foldin(ials_ctx* c, int32_t n_req, const int64_t* req_ptr, const int32_t* items, const float* y,
+                        int32_t passes, float* W_out) {
+    if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    if (n_req < 0 || passes < 0 || passes > 1000) return fail(c, IALS_E_INVALID, "need n_req >= 0 and 0 <= passes <= 1000");
+    if (n_req == 0) return IALS_OK;
+    if (!req_ptr || !W_out) return fail(c, IALS_E_INVALID, "null req_ptr or W_out");
+    if (req_ptr[0] != 0) return fail(c, IALS_E_INVALID, "req_ptr[0] must be 0");
+    for (int32_t r = 0; r < n_req; ++r)
+        if (req_ptr[r + 1] < req_ptr[r] || req_ptr[r + 1] - req_ptr[r] > (int64_t)INT32_MAX)
+            return fail(c, IALS_E_INVALID, "req_ptr must be non-decreasing with requests below 2^31 items");
+    if (req_ptr[n_req] > 0 && !items) return fail(c, IALS_E_INVALID, "null items");
+    if (c->fold_G_passes != c->passes) {
+        ials::launch_gramian_slab(c, c->H, c->I, 0, c->d, c->d, c->fold_G, false);
+        c->fold_G_passes = c->passes;
+    }
+    IALS_HIP_TRY(c, hipMemsetAsync(c->fold_cnt, 0, sizeof(int32_t) * ials::FOLD_CNT_NUM, c->stream));
+    int32_t r = 0;
+    while (r < n_req) {
+        int32_t m = 0;
+        size_t used = 0;
+        while (r + m < n_req && m < c->fold_req_cap) {
+            const int64_t lo = req_ptr[r + m], n = req_ptr[r + m + 1] - lo;
+            const size_t need = ials::fold_ws_floats(c->fold, n);
+            if (used + need > c->fold_ws_cap) break;
+            ials::FoldReq& q = c->fold_req[m];
+            q.items = items + lo;
+            q.y = y ? y + lo : nullptr;
+            q.ws = c->fold_ws + used;
+            q.out = W_out + (size_t)(r + m) * c->d;
+            q.st = nullptr;
+            q.n = (int32_t)n;
+            q.copy = 0;
+            used += need;
+            ++m;
+        }
+        if (m == 0)
+            return fail(c, IALS_E_INVALID, "request " + std::to_string(r) + " has more items than the fold-in scratch holds");
+        void* dreq = nullptr;
+        IALS_HIP_TRY(c, hipHostGetDevicePointer(&dreq, c->fold_req, 0));
+        IALS_HIP_TRY(c, ials::launch_foldin(c->stream, c->fold, c->H, c->fold_G, c->alpha0, c->lambda, c->tau, passes,
+                                            static_cast<const ials::FoldReq*>(dreq), m, c->fold_cnt));
+        // the descriptors and the scratch are reused by the next chunk
+        IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+        r += m;
+    }
+    int32_t cnt[ials::FOLD_CNT_NUM];
+    IALS_HIP_TRY(c, hipMemcpyAsync(cnt, c->fold_cnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->fold_requests += n_req;
+    c->fold_float64 += cnt[ials::FOLD_CNT_FLOAT64];
+    if (cnt[ials::FOLD_CNT_BAD_ID] > 0)
+        return fail(c, IALS_E_INVALID, std::to_string(cnt[ials::FOLD_CNT_BAD_ID]) + " requests hold item ids out of range");
+    if (cnt[ials::FOLD_CNT_NOT_SPD] > 0)
+        return fail(c, IALS_E_NOT_SPD, std::to_string(cnt[ials::FOLD_CNT_NOT_SPD]) +
+                                           " requests had a block Hessian that was not SPD in float64");
     return IALS_OK;
 }
 

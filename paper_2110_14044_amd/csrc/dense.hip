@@ -386,11 +386,9 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
                            inside, c->yhat, out);
 }
 
-// out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw); with make_dmat
-// also forms Dmat for the pass and resets the sweep cursors.
-void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols, float* out,
-                         bool make_dmat) {
-    const int32_t d = c->d;
+// out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw).
+void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
+                        float* part, float* out) {
     const int64_t ft = (d + 63) / 64;
     const int qt16 = (ncols + 15) / 16;
     const int QT = qt16 >= 4 ? 4 : (qt16 >= 2 ? 2 : 1);
@@ -399,14 +397,20 @@ void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
     if (QT == 4)
-        hipLaunchKernelGGL(k_gram_part<4>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+        hipLaunchKernelGGL(k_gram_part<4>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
     else if (QT == 2)
-        hipLaunchKernelGGL(k_gram_part<2>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+        hipLaunchKernelGGL(k_gram_part<2>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
     else
-        hipLaunchKernelGGL(k_gram_part<1>, grid, dim3(64), 0, c->stream, n, d, X, p0, bw, ncols, rows, c->gram_part);
+        hipLaunchKernelGGL(k_gram_part<1>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
     const int64_t count = (int64_t)d * ncols;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, c->stream, c->gram_part, (int32_t)chunks,
-                       count, out);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)chunks, count, out);
+}
+
+// The same on the context's stream and scratch; with make_dmat also forms Dmat for
+// the pass and resets the sweep cursors.
+void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols, float* out,
+                         bool make_dmat) {
+    launch_gramian_raw(c->stream, X, n, c->d, p0, bw, ncols, c->gram_part, out);
     if (make_dmat)
         hipLaunchKernelGGL(k_make_dmat, dim3(nblk(std::max(c->B * c->B, (int)CUR_NUM), 256)), dim3(256), 0, c->stream,
                            out, c->B, p0, bw, c->alpha0, c->lambda, c->Dmat, c->cursors);

@@ -47,6 +47,27 @@ struct SideIndex {
     int64_t max_len = 0;
 };
 
+// One fold-in request as the fold-in kernel reads it (from device or pinned host memory).
+struct FoldReq {
+    const int32_t* items;  // [n] item ids
+    const float* y;        // [n] labels (null: ones)
+    float* ws;             // device scratch of fold_ws_floats(n) floats, 256-byte aligned
+    float* out;            // [d] the folded-in row (device or pinned host memory)
+    int32_t* st;           // per-request status bits (FOLD_ST_*), may be null
+    int32_t n;
+    int32_t copy;          // 1: items / y are first copied into ws (host-resident inputs)
+};
+enum FoldStatus : int { FOLD_ST_FLOAT64 = 1, FOLD_ST_NOT_SPD = 2, FOLD_ST_BAD_ID = 4 };
+// Global fold-in counters (int32): bad ids, requests redone in float64, not SPD in float64.
+enum FoldCounter : int { FOLD_CNT_BAD_ID = 0, FOLD_CNT_FLOAT64 = 1, FOLD_CNT_NOT_SPD = 2, FOLD_CNT_NUM = 4 };
+
+// Launch shape of the fold-in kernel for one (item table, d, b).
+struct FoldShape {
+    int32_t I = 0, d = 0, b = 0, nb = 0, B = 0;
+    bool gfac = false;     // the Cholesky factors live in ws instead of LDS
+    size_t lds_bytes = 0;  // dynamic LDS per workgroup
+};
+
 }  // namespace ials
 
 struct ials_ctx {
@@ -89,8 +110,20 @@ struct ials_ctx {
     uint64_t budget = 0;
     int64_t passes = 0;
 
+    // fold-in of new rows against H (ials_foldin)
+    ials::FoldShape fold;
+    float* fold_G = nullptr;          // [d * d] H^T H
+    int64_t fold_G_passes = -1;       // pass count when fold_G was formed
+    float* fold_ws = nullptr;         // request scratch
+    size_t fold_ws_cap = 0;           // floats
+    ials::FoldReq* fold_req = nullptr;  // pinned host descriptors
+    int32_t fold_req_cap = 0;
+    int32_t* fold_cnt = nullptr;      // [FOLD_CNT_NUM] device counters
+    int64_t fold_requests = 0, fold_float64 = 0;
+
     std::string err;
-    std::vector<void*> owned;  // every device allocation of this context
+    std::vector<void*> owned;       // every device allocation of this context
+    std::vector<void*> owned_host;  // pinned host allocations
 
     // per-kernel timing (HIP events on the stream), off by default
     bool prof = false;
@@ -132,6 +165,14 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
 void launch_sweep(ials_ctx* c, int side, int32_t blk);
 ials_status launch_loss(ials_ctx* c);
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
+// out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats).
+void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
+                        float* part, float* out);
+FoldShape fold_shape(int32_t I, int32_t d, int32_t b);
+size_t fold_ws_floats(const FoldShape& f, int64_t n);
+// Fold-in of m requests (one workgroup each) against H (I x d) and G = H^T H (d x d).
+hipError_t launch_foldin(hipStream_t st, const FoldShape& f, const float* H, const float* G, float alpha0,
+                         float lambda, float tau, int32_t passes, const FoldReq* reqs, int32_t m, int32_t* counters);
 size_t seg_part_floats_per_segment(int32_t B);
 
 // Allocation helper that tracks the context's byte count and budget.

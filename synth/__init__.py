@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "workload", "user_lengths", "sample_histories",
     "make_observations", "init_embeddings", "Problem", "make_problem",
-    "random_labels", "serving_requests", "poisson_arrivals",
+    "random_labels", "serving_requests", "serving_table", "poisson_arrivals",
 ]
 
 
@@ -256,6 +256,11 @@ def serving_requests(seed: int, n_requests: int, num_items: int = 41_000, mu: fl
     ptr = np.zeros(n_requests + 1, np.int64)
     ptr[1:] = np.cumsum(n)
     return ptr, item
+
+
+def serving_table(seed: int, num_items: int = 41_000, dim: int = 256) -> np.ndarray:
+    """The fixed item table of the serving workload: N(0, 0.1/sqrt(d)) float32."""
+    return init_embeddings(np.random.Generator(np.random.PCG64(seed)), num_items, dim)
 
 
 def poisson_arrivals(seed: int, n: int, rate_per_s: float) -> np.ndarray:

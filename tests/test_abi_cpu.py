@@ -67,3 +67,33 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.ials_destroy(None) == binding.IALS_E_INVALID
     L = C.c_double()
     assert lib.ials_loss(None, C.byref(L), None) == binding.IALS_E_INVALID
+
+
+def test_server_create_rejects_bad_config_before_device_work(lib):
+    bad = [binding.make_server_config(0, 256, 64, 0.1, 0.05),          # no items
+           binding.make_server_config(100, 256, 0, 0.1, 0.05),         # b = 0
+           binding.make_server_config(100, 256, 65, 0.1, 0.05),        # b > 64
+           binding.make_server_config(100, 16, 32, 0.1, 0.05),         # b > d
+           binding.make_server_config(100, 256, 64, 0.1, 0.0),        # lambda = 0
+           binding.make_server_config(100, 256, 64, -0.1, 0.05),       # alpha0 < 0
+           binding.make_server_config(100, 256, 64, 0.1, 0.05, passes=-1),
+           binding.make_server_config(100, 256, 64, 0.1, 0.05, max_slots=0),
+           binding.make_server_config(100, 256, 64, 0.1, 0.05, streams=9),
+           binding.make_server_config(100, 256, 64, 0.1, 0.05, hbm_budget=1000),
+           binding.make_server_config(100, 256, 64, 0.1, 0.05, precision=binding.IALS_PREC_BF16)]
+    for cfg in bad:
+        out = C.c_void_p()
+        assert lib.ials_server_create(C.byref(cfg), 1, C.byref(out)) == binding.IALS_E_INVALID
+        assert out.value is None
+        assert binding.ials_server_last_error(None)
+    cfg = binding.make_server_config(100, 256, 64, 0.1, 0.05)
+    out = C.c_void_p()
+    assert lib.ials_server_create(C.byref(cfg), None, C.byref(out)) == binding.IALS_E_INVALID
+
+
+def test_null_server_and_foldin_calls_fail_cleanly(lib):
+    n = C.c_int32()
+    assert lib.ials_server_submit(None, 0, None, None, 0) == binding.IALS_E_INVALID
+    assert lib.ials_server_poll(None, 1, 0, None, None, None, C.byref(n)) == binding.IALS_E_INVALID
+    assert lib.ials_server_destroy(None) == binding.IALS_E_INVALID
+    assert lib.ials_foldin(None, 0, None, None, None, 3, None) == binding.IALS_E_INVALID
