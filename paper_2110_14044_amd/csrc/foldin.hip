@@ -10,15 +10,18 @@
 //   w[pi] -= Hess^-1 grad,   yhat_k -= <delta, h_{i_k}[pi]>
 // with G = H^T H.  H is fixed, so every block's Hessian is the same in every
 // sweep: it is accumulated on the matrix cores and Cholesky-factored once per
-// request, and each block step is then a gradient, two triangular solves and
-// the updates.
+// request, and the factor is inverted (X = L^-1, lower triangular), so that a
+// block step is a gradient, two small matrix-vector products
+// (delta = X^T (X grad)) and the updates, with no sequential solve.
 //
-// One workgroup (4 wavefronts) per request.  Phase 1: the waves factor blocks
-// in parallel (wave v takes blocks v, v+4, ...), keeping the factors in LDS
-// (or in the request's scratch when they do not fit).  Phase 2: the block
-// steps in order; the observed part of the gradient, the update of alpha0 w G
-// and of the predictions are spread over the workgroup, the solve runs on one
-// wavefront.  A request whose float32 pivots fail the ratio test is redone in
+// One workgroup (4 wavefronts) per request.  Phase 1: the waves factor and
+// invert blocks in parallel (wave v takes blocks v, v+4, ...), keeping X in
+// LDS (or in the request's scratch when it does not fit).  Phase 2: the block
+// steps in order, one workgroup barrier each: every wave sums its share of the
+// gradient, then every wave forms the same step from the four partial sums
+// (the same operations in the same order, so the four copies of w agree bit
+// for bit).  The ids and residuals yhat - y of a request of up to nl items stay
+// in LDS.  A request whose float32 pivots fail the ratio test is redone in
 // float64 from scratch by the whole workgroup (the same iteration, with each
 // block's Hessian rebuilt, factored and solved in float64).
 #include <hip/hip_runtime.h>
@@ -37,6 +40,7 @@ struct FoldArgs {
     float alpha0, lambda, tau;
     int32_t passes;
     int32_t m;
+    int32_t nl;  // requests of up to nl items keep their ids and residuals in LDS
     const FoldReq* req;
     int32_t* cnt;  // FOLD_CNT_NUM counters (may be null)
 };
@@ -163,61 +167,78 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
     extern __shared__ __align__(16) float sm[];
     const int tid = threadIdx.x, lane = tid & 63, q16 = lane & 15, g4 = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int d = A.d, dp = (d + 3) & ~3;
-    float* w = sm;                 // [dp]  the row being folded in
-    float* u = w + dp;             // [dp]  alpha0 * w G
-    float* part = u + dp;          // [4][B] per-wave gradient partials
-    float* dl = part + 4 * B;      // [B]   the step
-    int* flag = reinterpret_cast<int*>(dl + B);  // [4]: float64 redo, bad id, not SPD
-    float* tail = reinterpret_cast<float*>(flag + 4);  // factors (LDS mode) or the float64 work area
+    const int d = A.d, dp = (d + 3) & ~3, nl = A.nl;
+    float* wv = sm;                // [4][dp] each wave's copy of the row being folded in
+    float* part = wv + 4 * dp;     // [2][4][B] per-wave gradient partials (double-buffered by step)
+    float* gv = part + 8 * B;      // [4][B] per-wave gradient
+    float* tv = gv + 4 * B;        // [4][B] per-wave X g
+    float* dv = tv + 4 * B;        // [4][B] per-wave step delta
+    int* flag = reinterpret_cast<int*>(dv + 4 * B);            // [4]: float64 redo, bad id, not SPD
+    int32_t* items_l = reinterpret_cast<int32_t*>(flag + 4);  // [nl] ids of a request of <= nl items
+    float* res_l = reinterpret_cast<float*>(items_l + nl);    // [nl] its residuals yhat - y
+    float* tail = res_l + nl;      // inverse factors (LDS mode) or the float64 work area
+    float* wme = wv + wave * dp;
+    float* gme = gv + wave * B;
+    float* tme = tv + wave * B;
+    float* dme = dv + wave * B;
 
     for (int r = blockIdx.x; r < A.m; r += gridDim.x) {
         const FoldReq R = A.req[r];
         const int n = R.n;
-        float* yh = R.ws;
-        const int32_t* items = R.copy ? reinterpret_cast<const int32_t*>(R.ws + ws_items_off(n)) : R.items;
+        const bool in_lds = n <= nl;
+        int32_t* ids_w = in_lds ? items_l : reinterpret_cast<int32_t*>(R.ws + ws_items_off(n));
+        const int32_t* items = (in_lds || R.copy) ? ids_w : R.items;
+        float* res = in_lds ? res_l : R.ws;
         const float* yv = R.y ? (R.copy ? R.ws + ws_y_off(n) : R.y) : nullptr;
         float* fac = GFAC ? R.ws + ws_fac_off(n) : tail;
 
-        // phase 0: w = 0, predictions = 0, inputs staged and checked
-        for (int f = tid; f < dp; f += 256) {
-            w[f] = 0.f;
-            u[f] = 0.f;
-        }
+        // phase 0: w = 0; residuals yhat - y = -y; ids (and labels) staged and checked
+        for (int f = tid; f < 4 * dp; f += 256) wv[f] = 0.f;
         if (tid < 4) flag[tid] = 0;
         __syncthreads();
         for (int k = tid; k < n; k += 256) {
             const int it = R.items[k];
             if ((unsigned)it >= (unsigned)A.I) flag[1] = 1;
-            if (R.copy) {
-                reinterpret_cast<int32_t*>(R.ws + ws_items_off(n))[k] = it;
-                if (R.y) R.ws[ws_y_off(n) + k] = R.y[k];
-            }
-            yh[k] = 0.f;
+            const float yk = R.y ? R.y[k] : 1.f;
+            if (in_lds || R.copy) ids_w[k] = it;
+            if (R.copy && R.y) R.ws[ws_y_off(n) + k] = yk;
+            res[k] = -yk;
         }
         __syncthreads();
 
-        // phase 1: factor every block's Hessian (wave v: blocks v, v+4, ...)
+        // phase 1: every block's Hessian, its Cholesky factor L and X = L^-1
+        // (wave v: blocks v, v+4, ...)
         for (int blk = wave; blk < A.nb; blk += 4) {
             const int p0 = blk * A.b, bw = min(A.b, d - p0);
             floatx4 acc[NTL];
 #pragma unroll
             for (int id = 0; id < NTL; ++id) acc[id] = floatx4{0.f, 0.f, 0.f, 0.f};
-            for (int k0 = 0; k0 < n; k0 += 4) {
-                const int k = k0 + g4;
-                const bool v = k < n;
-                const float* hr = A.H + (size_t)(v ? item_at(items, k, A.I) : 0) * d + p0;
-                float x[NT];
+            // 16 MFMA steps of 4 observations per round, their loads issued together
+            for (int k0 = 0; k0 < n; k0 += 64) {
+                int idr[16];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const int c = 16 * t + q16;
-                    const float h = hr[c < bw ? c : 0];
-                    x[t] = (v && c < bw) ? h : 0.f;
+                for (int s16 = 0; s16 < 16; ++s16) {
+                    const int k = k0 + 4 * s16 + g4;
+                    idr[s16] = k < n ? item_at(items, k, A.I) : -1;
+                }
+                float x[16][NT];
+#pragma unroll
+                for (int s16 = 0; s16 < 16; ++s16) {
+                    const float* hr = A.H + (size_t)(idr[s16] >= 0 ? idr[s16] : 0) * d + p0;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const int c = 16 * t + q16;
+                        const float h = hr[c < bw ? c : 0];
+                        x[s16][t] = (idr[s16] >= 0 && c < bw) ? h : 0.f;
+                    }
                 }
 #pragma unroll
-                for (int I = 0; I < NT; ++I)
+                for (int s16 = 0; s16 < 16; ++s16)
 #pragma unroll
-                    for (int J = 0; J <= I; ++J) acc[I * (I + 1) / 2 + J] = mfma4(x[I], x[J], acc[I * (I + 1) / 2 + J]);
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int J = 0; J <= I; ++J)
+                            acc[I * (I + 1) / 2 + J] = mfma4(x[s16][I], x[s16][J], acc[I * (I + 1) / 2 + J]);
             }
             float* L = fac + (size_t)blk * B * PB;
             // lower tiles plus alpha0 G[pi,pi] + lambda I (identity on the padding)
@@ -257,100 +278,145 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
 #pragma unroll
                 for (int j = k + 1; j < B; ++j) a[j] = fmaf(-l, readlane(l, j), a[j]);
             }
+            const bool bad = !(pmin > 0.f) || pmin < A.tau * pmax;
+            if (bad && lane == 0) flag[0] = 1;
+            // X = L^-1 by columns, lane j holding column j: X_jj = 1/L_jj and, for i > j,
+            // X_ij = -(sum_{j <= k < i} L_ik X_kj) / L_ii (row i of L is lane i's registers).
+            float x[B];
+#pragma unroll
+            for (int ii = 0; ii < B; ++ii) {
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int k = 0; k + 1 < ii; k += 2) {
+                    s0 = fmaf(readlane(a[k], ii), x[k], s0);
+                    s1 = fmaf(readlane(a[k + 1], ii), x[k + 1], s1);
+                }
+                if (ii & 1) s0 = fmaf(readlane(a[ii - 1], ii), x[ii - 1], s0);
+                const float di = 1.f / readlane(a[ii], ii);
+                x[ii] = (ii < lane) ? 0.f : (ii == lane ? di : -(s0 + s1) * di);
+            }
+            wave_fence();
             if (lane < B) {
 #pragma unroll
-                for (int k = 0; k < B; ++k) L[lane * PB + k] = a[k];
+                for (int ii = 0; ii < B; ++ii) L[ii * PB + lane] = x[ii];
             }
-            if ((!(pmin > 0.f) || pmin < A.tau * pmax) && lane == 0) flag[0] = 1;
         }
         __syncthreads();
 
         if (flag[0]) {
             foldin_f64<B>(A, R, n, items, yv, reinterpret_cast<double*>(tail), &flag[2]);
         } else {
-            // phase 2: the block steps, sweep after sweep
+            // phase 2: the block steps, sweep after sweep.  Each wave sums its part of the
+            // gradient (a quarter of the rows of G, every fourth observation), then every wave
+            // forms the same step from the four partials and applies it to its own copy of w,
+            // so one barrier per step suffices.  A wave also owns the residuals of its
+            // observations: it applies the previous step to them just before they are used.
             const bool vec = (d % 4 == 0) && (A.b % 4 == 0);
+            const int nv = n > wave ? (n - wave + 3) / 4 : 0;  // observations wave, wave+4, ...
+            const int fq = (d + 3) / 4, f_lo = min(d, wave * fq), f_hi = min(d, f_lo + fq);
+            int step = 0, pp0 = 0, pbw = 0;
             for (int pass = 0; pass < A.passes; ++pass) {
-                for (int blk = 0; blk < A.nb; ++blk) {
+                for (int blk = 0; blk < A.nb; ++blk, ++step) {
                     const int p0 = blk * A.b, bw = min(A.b, d - p0);
-                    // observed part of the gradient: wave v takes observations v, v+4, ...
-                    {
-                        const bool cj = lane < bw;
-                        float s0 = 0.f, s1 = 0.f;
-                        int k = wave;
-                        for (; k + 4 < n; k += 8) {
-                            const int i0 = item_at(items, k, A.I), i1 = item_at(items, k + 4, A.I);
-                            const float r0 = yh[k] - (yv ? yv[k] : 1.f);
-                            const float r1 = yh[k + 4] - (yv ? yv[k + 4] : 1.f);
-                            const float h0 = A.H[(size_t)i0 * d + p0 + (cj ? lane : 0)];
-                            const float h1 = A.H[(size_t)i1 * d + p0 + (cj ? lane : 0)];
-                            s0 = fmaf(r0, cj ? h0 : 0.f, s0);
-                            s1 = fmaf(r1, cj ? h1 : 0.f, s1);
+                    const float* X = fac + (size_t)blk * B * PB;
+                    const int col = p0 + (lane < bw ? lane : 0);
+                    // dense part: alpha0 sum_f w_f G[f][p0 + lane] over this wave's rows f
+                    float sd0 = 0.f, sd1 = 0.f;
+                    for (int f = f_lo; f < f_hi; f += 16) {
+                        float gg[16];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) gg[q] = A.G[(size_t)min(f + q, f_hi - 1) * d + col];
+#pragma unroll
+                        for (int q = 0; q < 16; q += 2) {
+                            const float w0 = (f + q < f_hi) ? wme[f + q] : 0.f;
+                            const float w1 = (f + q + 1 < f_hi) ? wme[f + q + 1] : 0.f;
+                            sd0 = fmaf(w0, gg[q], sd0);
+                            sd1 = fmaf(w1, gg[q + 1], sd1);
                         }
+                    }
+                    // observations: previous step applied to the residuals, then res_k h_k[p0 + lane]
+                    float so0 = 0.f, so1 = 0.f;
+                    for (int m0 = 0; m0 < nv; m0 += 64) {
+                        const int k = wave + 4 * (m0 + lane);
+                        int itl = 0;
+                        float rl = 0.f;
                         if (k < n) {
-                            const int i0 = item_at(items, k, A.I);
-                            const float r0 = yh[k] - (yv ? yv[k] : 1.f);
-                            const float h0 = A.H[(size_t)i0 * d + p0 + (cj ? lane : 0)];
-                            s0 = fmaf(r0, cj ? h0 : 0.f, s0);
-                        }
-                        if (lane < B) part[wave * B + lane] = s0 + s1;
-                    }
-                    __syncthreads();
-                    if (wave == 0) {
-                        const int i = lane < B ? lane : 0;
-                        float g = 0.f;
-                        if (lane < bw)
-                            g = u[p0 + lane] + A.lambda * w[p0 + lane] +
-                                ((part[lane] + part[B + lane]) + (part[2 * B + lane] + part[3 * B + lane]));
-                        const float* L = fac + (size_t)blk * B * PB;
-                        float lr[B], lc[B];
-#pragma unroll
-                        for (int k = 0; k < B; ++k) {
-                            lr[k] = L[i * PB + k];  // row i of L
-                            lc[k] = L[k * PB + i];  // column i of L
-                        }
-                        const float dinv = 1.f / L[i * PB + i];
-                        // L y = g, then L^T delta = y
-#pragma unroll
-                        for (int k = 0; k < B; ++k) {
-                            const float yk = readlane(g, k) * readlane(dinv, k);
-                            g = (lane > k) ? fmaf(-lr[k], yk, g) : (lane == k ? yk : g);
-                        }
-#pragma unroll
-                        for (int k = B - 1; k >= 0; --k) {
-                            const float xk = readlane(g, k) * readlane(dinv, k);
-                            g = (lane < k) ? fmaf(-lc[k], xk, g) : (lane == k ? xk : g);
-                        }
-                        if (lane < B) dl[lane] = lane < bw ? g : 0.f;
-                        if (lane < bw) w[p0 + lane] -= g;
-                    }
-                    __syncthreads();
-                    // u -= alpha0 delta G[pi, :]   and   yhat_k -= <delta, h_k[pi]>
-                    for (int f = tid; f < d; f += 256) {
-                        float s = 0.f;
-                        for (int j = 0; j < bw; ++j) s = fmaf(dl[j], A.G[(size_t)(p0 + j) * d + f], s);
-                        u[f] = fmaf(-A.alpha0, s, u[f]);
-                    }
-                    for (int k = tid; k < n; k += 256) {
-                        const float* hr = A.H + (size_t)item_at(items, k, A.I) * d + p0;
-                        float s = 0.f;
-                        if (vec) {
-                            for (int j = 0; j < bw; j += 4) {
-                                const float4 h = *reinterpret_cast<const float4*>(hr + j);
-                                s = fmaf(dl[j], h.x, s);
-                                s = fmaf(dl[j + 1], h.y, s);
-                                s = fmaf(dl[j + 2], h.z, s);
-                                s = fmaf(dl[j + 3], h.w, s);
+                            itl = item_at(items, k, A.I);
+                            rl = res[k];
+                            if (step > 0) {
+                                const float* hr = A.H + (size_t)itl * d + pp0;
+                                float e0 = 0.f, e1 = 0.f;
+                                if (vec) {
+                                    for (int j = 0; j < pbw; j += 8) {
+                                        const float4 h0 = *reinterpret_cast<const float4*>(hr + j);
+                                        const float4 h1 = (j + 4 < pbw) ? *reinterpret_cast<const float4*>(hr + j + 4)
+                                                                        : float4{0.f, 0.f, 0.f, 0.f};
+                                        e0 = fmaf(dme[j], h0.x, e0);
+                                        e0 = fmaf(dme[j + 1], h0.y, e0);
+                                        e0 = fmaf(dme[j + 2], h0.z, e0);
+                                        e0 = fmaf(dme[j + 3], h0.w, e0);
+                                        e1 = fmaf(dme[j + 4], h1.x, e1);
+                                        e1 = fmaf(dme[j + 5], h1.y, e1);
+                                        e1 = fmaf(dme[j + 6], h1.z, e1);
+                                        e1 = fmaf(dme[j + 7], h1.w, e1);
+                                    }
+                                } else {
+                                    for (int j = 0; j < pbw; ++j) e0 = fmaf(dme[j], hr[j], e0);
+                                }
+                                rl -= e0 + e1;
+                                res[k] = rl;
                             }
-                        } else {
-                            for (int j = 0; j < bw; ++j) s = fmaf(dl[j], hr[j], s);
                         }
-                        yh[k] -= s;
+                        const int cnt = min(64, nv - m0);
+                        for (int t = 0; t < cnt; t += 8) {
+                            float h[8], rr[8];
+#pragma unroll
+                            for (int s8 = 0; s8 < 8; ++s8) {
+                                const int it = __builtin_amdgcn_readlane(itl, t + s8);
+                                rr[s8] = readlane(rl, t + s8);
+                                h[s8] = A.H[(size_t)it * d + col];
+                            }
+#pragma unroll
+                            for (int s8 = 0; s8 < 8; s8 += 2) {
+                                so0 = fmaf(rr[s8], h[s8], so0);
+                                so1 = fmaf(rr[s8 + 1], h[s8 + 1], so1);
+                            }
+                        }
                     }
+                    float* pb = part + (step & 1) * 4 * B;
+                    if (lane < B) pb[wave * B + lane] = lane < bw ? A.alpha0 * (sd0 + sd1) + (so0 + so1) : 0.f;
                     __syncthreads();
+                    // every wave: gradient, delta = X^T (X g) = Hess^-1 g, its copy of w updated
+                    if (lane < B)
+                        gme[lane] = lane < bw ? ((pb[lane] + pb[B + lane]) + (pb[2 * B + lane] + pb[3 * B + lane])) +
+                                                    A.lambda * wme[p0 + lane]
+                                              : 0.f;
+                    wave_fence();
+                    const int i = lane < B ? lane : 0;
+                    float t0 = 0.f, t1 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < B; k += 2) {
+                        t0 = fmaf(X[i * PB + k], gme[k], t0);
+                        t1 = fmaf(X[i * PB + k + 1], gme[k + 1], t1);
+                    }
+                    if (lane < B) tme[lane] = t0 + t1;
+                    wave_fence();
+                    float e0 = 0.f, e1 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < B; k += 2) {
+                        e0 = fmaf(X[k * PB + i], tme[k], e0);
+                        e1 = fmaf(X[(k + 1) * PB + i], tme[k + 1], e1);
+                    }
+                    const float del = e0 + e1;
+                    if (lane < B) dme[lane] = lane < bw ? del : 0.f;
+                    if (lane < bw) wme[p0 + lane] -= del;
+                    wave_fence();
+                    pp0 = p0;
+                    pbw = bw;
                 }
             }
-            for (int f = tid; f < d; f += 256) R.out[f] = w[f];
+            if (wave == 0)
+                for (int f = lane; f < d; f += 64) R.out[f] = wme[f];
         }
         __syncthreads();
         if (tid == 0) {
@@ -369,7 +435,7 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
 
 constexpr size_t kFoldLdsMax = 150 * 1024;
 
-size_t lds_head_bytes(int32_t d, int32_t B) { return (size_t)(2 * ((d + 3) & ~3) + 5 * B + 4) * 4; }
+size_t lds_head_bytes(int32_t d, int32_t B, int32_t nl) { return (size_t)(4 * ((d + 3) & ~3) + 20 * B + 4 + 2 * nl) * 4; }
 size_t lds_f64_bytes(int32_t d, int32_t B) { return (size_t)(B * B + ((d + 3) & ~3) + 2 * B) * 8; }
 size_t lds_fac_bytes(int32_t nb, int32_t B) { return (size_t)nb * B * (B + 1) * 4; }
 
@@ -392,9 +458,23 @@ FoldShape fold_shape(int32_t I, int32_t d, int32_t b) {
     f.b = b;
     f.nb = (d + b - 1) / b;
     f.B = (b + 15) / 16 * 16;
-    const size_t head = lds_head_bytes(d, f.B), f64 = lds_f64_bytes(d, f.B), fac = lds_fac_bytes(f.nb, f.B);
-    f.gfac = head + std::max(fac, f64) > kFoldLdsMax;
-    f.lds_bytes = head + (f.gfac ? f64 : std::max(fac, f64));
+    const size_t f64 = lds_f64_bytes(d, f.B), fac = lds_fac_bytes(f.nb, f.B);
+    static const int32_t kNl[] = {2048, 1024, 256, 0};
+    for (int gfac = 0; gfac < 2; ++gfac) {
+        const size_t rest = gfac ? f64 : std::max(fac, f64);
+        for (int32_t nl : kNl) {
+            const size_t bytes = lds_head_bytes(d, f.B, nl) + rest;
+            if (bytes <= kFoldLdsMax) {
+                f.gfac = gfac != 0;
+                f.nl = nl;
+                f.lds_bytes = bytes;
+                return f;
+            }
+        }
+    }
+    f.gfac = true;
+    f.nl = 0;
+    f.lds_bytes = lds_head_bytes(d, f.B, 0) + f64;  // above the limit: launch_foldin refuses it
     return f;
 }
 
@@ -407,7 +487,7 @@ hipError_t launch_foldin(hipStream_t st, const FoldShape& f, const float* H, con
                          float lambda, float tau, int32_t passes, const FoldReq* reqs, int32_t m, int32_t* counters) {
     if (m <= 0) return hipSuccess;
     if (f.lds_bytes > kFoldLdsMax) return hipErrorInvalidValue;
-    FoldArgs a{H, G, f.I, f.d, f.b, f.nb, alpha0, lambda, tau, passes, m, reqs, counters};
+    FoldArgs a{H, G, f.I, f.d, f.b, f.nb, alpha0, lambda, tau, passes, m, f.nl, reqs, counters};
     switch (f.B) {
         case 16: return f.gfac ? launch_nt<1, true>(st, f, a) : launch_nt<1, false>(st, f, a);
         case 32: return f.gfac ? launch_nt<2, true>(st, f, a) : launch_nt<2, false>(st, f, a);

@@ -64,7 +64,8 @@ enum FoldCounter : int { FOLD_CNT_BAD_ID = 0, FOLD_CNT_FLOAT64 = 1, FOLD_CNT_NOT
 // Launch shape of the fold-in kernel for one (item table, d, b).
 struct FoldShape {
     int32_t I = 0, d = 0, b = 0, nb = 0, B = 0;
-    bool gfac = false;     // the Cholesky factors live in ws instead of LDS
+    bool gfac = false;     // the inverse factors live in ws instead of LDS
+    int32_t nl = 0;        // requests of up to nl items keep ids and residuals in LDS
     size_t lds_bytes = 0;  // dynamic LDS per workgroup
 };
 
