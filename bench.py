@@ -145,6 +145,45 @@ def serving_bench(n_req, warm, rates):
     return out
 
 
+def matched_loss(p, epochs):
+    """Plain FP32 form against the bfloat16 form on the same workload at the same b: the FP32
+    form runs `epochs` epochs to a final loss L*; the bfloat16 form is timed until its loss is
+    within L*(1 + 1e-3).  Epochs are replayed from each context's epoch graph and timed one by
+    one (synchronised, launched kernel by kernel so that no graph capture falls inside an
+    epoch); the losses are evaluated outside the timed epochs."""
+    import torch
+    from paper_2110_14044_amd import Trainer, binding
+    out = {}
+    for name, prec in (("fp32", binding.IALS_PREC_FP32), ("bf16", binding.IALS_PREC_BF16)):
+        warm = Trainer(p, precision=prec)  # loads this form's kernels before the timed context
+        warm.epoch(1)
+        warm.close()
+        tr = Trainer(p, precision=prec)
+        times, losses = [], []
+        for t in range(epochs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr.epoch(1)
+            tr.synchronize()
+            times.append(time.perf_counter() - t0)
+            losses.append(tr.loss()[0])
+        tr.close()
+        out[name] = {"epoch_s": times, "loss": losses}
+    Lstar = out["fp32"]["loss"][-1]
+    bl = out["bf16"]["loss"]
+    reach = next((e for e, L in enumerate(bl) if L <= Lstar * (1 + 1e-3)), None)
+    t32 = sum(out["fp32"]["epoch_s"])
+    res = {"epochs_fp32": epochs, "loss_fp32_final": Lstar,
+           "fp32_total_s": t32, "fp32_median_epoch_s": sorted(out["fp32"]["epoch_s"])[epochs // 2],
+           "bf16_median_epoch_s": sorted(out["bf16"]["epoch_s"])[epochs // 2],
+           "bf16_epochs_to_match": None if reach is None else reach + 1,
+           "bf16_time_to_match_s": None if reach is None else sum(out["bf16"]["epoch_s"][:reach + 1]),
+           "loss_rel_diff_per_epoch": [abs(a - b) / b for a, b in zip(bl, out["fp32"]["loss"])]}
+    if reach is not None:
+        res["speedup_at_matched_loss"] = t32 / res["bf16_time_to_match_s"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +192,10 @@ def main():
     ap.add_argument("--workload", default="ml20m_like")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
+    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
+                    help="arithmetic of the timed epochs (the bf16 form: bfloat16 Hessian and Gramian products)")
+    ap.add_argument("--matched-loss-epochs", type=int, default=16,
+                    help="epochs of the FP32 vs BF16 matched-loss comparison (0 = skip)")
     ap.add_argument("--serving", choices=("on", "off", "only"), default="on",
                     help="fold-in serving measurement beside the training epochs")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -191,7 +234,8 @@ def main():
     p = synth.make_problem(args.workload)
     log(f"[bench] generated in {time.time() - t0:.1f}s; building the index on the GPU")
     torch.cuda.set_device(0)
-    tr = Trainer(p, graph=not args.no_graph)
+    prec = binding.IALS_PREC_BF16 if args.precision == "bf16" else binding.IALS_PREC_FP32
+    tr = Trainer(p, graph=not args.no_graph, precision=prec)
     torch.cuda.synchronize()
     st = tr.stats()
     log(f"[bench] index built: long rows user {st['long_rows_user']} item {st['long_rows_item']}, "
@@ -265,20 +309,26 @@ def main():
                "sample": f"one full epoch of {wl.name} (from W0, H0; includes the per-epoch loss), "
                          f"{t_cpu:.2f} s", "epoch_s": t_cpu}
 
+    tr.close()
+    matched = None
+    if args.matched_loss_epochs > 0:
+        log(f"[bench] matched-loss comparison: fp32 vs bf16, {args.matched_loss_epochs} epochs")
+        matched = matched_loss(p, args.matched_loss_epochs)
+        log(f"[bench] fp32 median epoch {matched['fp32_median_epoch_s'] * 1e3:.2f} ms, bf16 "
+            f"{matched['bf16_median_epoch_s'] * 1e3:.2f} ms; bf16 reaches L* in {matched['bf16_epochs_to_match']} epochs")
     serving = None
     if args.serving == "on":
-        tr.close()
         serving = serving_bench(args.serve_requests, args.serve_warmup, SERVE_RATES)
 
     out = {
         "metric": METRIC, "value": value, "unit": "nnz·b/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": epoch_s * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16" else "f32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.num_users} users x {wl.num_items} items, {wl.nnz} observations "
                                f"(y=alpha=1), d={wl.dim}, b={wl.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
                    "epoch_s": epoch_s, "parallelism": "single GPU"},
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
-        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "serving": serving,
+        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,
     }
     tr.close()
     print(json.dumps(out))

@@ -132,8 +132,8 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
         g_create_error = "need alpha0 >= 0 and lambda > 0 (finite)";
         return IALS_E_INVALID;
     }
-    if (cfg->precision != IALS_PREC_FP32) {
-        g_create_error = "only IALS_PREC_FP32 is available in this build";
+    if (cfg->precision != IALS_PREC_FP32 && cfg->precision != IALS_PREC_BF16) {
+        g_create_error = "precision must be IALS_PREC_FP32 or IALS_PREC_BF16";
         return IALS_E_INVALID;
     }
     if ((cfg->flags & ~(uint32_t)IALS_FLAG_GRAPH) != 0) {

@@ -118,8 +118,17 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
 
 // Partial Gramian of one row chunk: part[chunk][f][q] = sum_{r in chunk} X[r][f] X[r][p0+q]
 // for f < d, q < ncols (columns q >= bw are zero).  Block = one wavefront owning a
-// 64 x (16*QT) output tile (4 x QT MFMA tiles).
-template <int QT>
+// 64 x (16*QT) output tile (4 x QT MFMA tiles).  BF: bfloat16 operands (16 rows per
+// 16x16x16 MFMA, four rows per lane), float32 accumulation.
+__device__ inline unsigned bf16_bits(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline shortx4 bf16x4(const float* v) {
+    return shortx4{(short)bf16_bits(v[0]), (short)bf16_bits(v[1]), (short)bf16_bits(v[2]), (short)bf16_bits(v[3])};
+}
+
+template <int QT, bool BF>
 __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
                                                   int32_t bw, int32_t ncols, int32_t rows_per_chunk,
                                                   float* __restrict__ part) {
@@ -133,25 +142,57 @@ __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const fl
     for (int ft = 0; ft < 4; ++ft)
 #pragma unroll
         for (int qt = 0; qt < QT; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t r = r0; r < r1; r += 4) {
-        const int64_t rr = r + g4;
-        const bool v = rr < r1;
-        const float* xr = X + (size_t)(v ? rr : 0) * d;
-        float a[4], b[QT];
+    if constexpr (BF) {
+        for (int64_t r = r0; r < r1; r += 16) {
+            float a[4][4], b[QT][4];
 #pragma unroll
-        for (int ft = 0; ft < 4; ++ft) {
-            const int f = f0 + 16 * ft + q16;
-            a[ft] = (v && f < d) ? xr[f] : 0.f;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t rr = r + 4 * g4 + u;
+                const bool v = rr < r1;
+                const float* xr = X + (size_t)(v ? rr : 0) * d;
+#pragma unroll
+                for (int ft = 0; ft < 4; ++ft) {
+                    const int f = f0 + 16 * ft + q16;
+                    a[ft][u] = (v && f < d) ? xr[f] : 0.f;
+                }
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt) {
+                    const int q = qg0 + 16 * qt + q16;
+                    b[qt][u] = (v && q < bw) ? xr[p0 + q] : 0.f;
+                }
+            }
+            shortx4 pa[4], pb[QT];
+#pragma unroll
+            for (int ft = 0; ft < 4; ++ft) pa[ft] = bf16x4(a[ft]);
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt) pb[qt] = bf16x4(b[qt]);
+#pragma unroll
+            for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt)
+                    acc[ft][qt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[ft], pb[qt], acc[ft][qt], 0, 0, 0);
         }
+    } else {
+        for (int64_t r = r0; r < r1; r += 4) {
+            const int64_t rr = r + g4;
+            const bool v = rr < r1;
+            const float* xr = X + (size_t)(v ? rr : 0) * d;
+            float a[4], b[QT];
 #pragma unroll
-        for (int qt = 0; qt < QT; ++qt) {
-            const int q = qg0 + 16 * qt + q16;
-            b[qt] = (v && q < bw) ? xr[p0 + q] : 0.f;
+            for (int ft = 0; ft < 4; ++ft) {
+                const int f = f0 + 16 * ft + q16;
+                a[ft] = (v && f < d) ? xr[f] : 0.f;
+            }
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt) {
+                const int q = qg0 + 16 * qt + q16;
+                b[qt] = (v && q < bw) ? xr[p0 + q] : 0.f;
+            }
+#pragma unroll
+            for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt) acc[ft][qt] = mfma4(a[ft], b[qt], acc[ft][qt]);
         }
-#pragma unroll
-        for (int ft = 0; ft < 4; ++ft)
-#pragma unroll
-            for (int qt = 0; qt < QT; ++qt) acc[ft][qt] = mfma4(a[ft], b[qt], acc[ft][qt]);
     }
     float* out = part + (size_t)chunk * d * ncols;
 #pragma unroll
@@ -388,7 +429,7 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
 
 // out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw).
 void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
-                        float* part, float* out) {
+                        float* part, float* out, bool bf16) {
     const int64_t ft = (d + 63) / 64;
     const int qt16 = (ncols + 15) / 16;
     const int QT = qt16 >= 4 ? 4 : (qt16 >= 2 ? 2 : 1);
@@ -396,12 +437,17 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
-    if (QT == 4)
-        hipLaunchKernelGGL(k_gram_part<4>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
-    else if (QT == 2)
-        hipLaunchKernelGGL(k_gram_part<2>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
-    else
-        hipLaunchKernelGGL(k_gram_part<1>, grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part);
+#define IALS_GRAM(Q, BFV) hipLaunchKernelGGL((k_gram_part<Q, BFV>), grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part)
+    if (bf16) {
+        if (QT == 4) IALS_GRAM(4, true);
+        else if (QT == 2) IALS_GRAM(2, true);
+        else IALS_GRAM(1, true);
+    } else {
+        if (QT == 4) IALS_GRAM(4, false);
+        else if (QT == 2) IALS_GRAM(2, false);
+        else IALS_GRAM(1, false);
+    }
+#undef IALS_GRAM
     const int64_t count = (int64_t)d * ncols;
     hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)chunks, count, out);
 }
@@ -410,7 +456,7 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
 // the pass and resets the sweep cursors.
 void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols, float* out,
                          bool make_dmat) {
-    launch_gramian_raw(c->stream, X, n, c->d, p0, bw, ncols, c->gram_part, out);
+    launch_gramian_raw(c->stream, X, n, c->d, p0, bw, ncols, c->gram_part, out, c->precision == IALS_PREC_BF16);
     if (make_dmat)
         hipLaunchKernelGGL(k_make_dmat, dim3(nblk(std::max(c->B * c->B, (int)CUR_NUM), 256)), dim3(256), 0, c->stream,
                            out, c->B, p0, bw, c->alpha0, c->lambda, c->Dmat, c->cursors);

@@ -12,6 +12,7 @@
 namespace ials {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 // Rows longer than this many observations are split into segments of kSegLen,
@@ -166,9 +167,10 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
 void launch_sweep(ials_ctx* c, int side, int32_t blk);
 ials_status launch_loss(ials_ctx* c);
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
-// out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats).
+// out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats);
+// bf16: bfloat16 operands on the matrix cores, float32 partials, float64 reduction.
 void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
-                        float* part, float* out);
+                        float* part, float* out, bool bf16);
 FoldShape fold_shape(int32_t I, int32_t d, int32_t b);
 size_t fold_ws_floats(const FoldShape& f, int64_t n);
 // Fold-in of m requests (one workgroup each) against H (I x d) and G = H^T H (d x d).

@@ -315,7 +315,7 @@ ials_status create_server(const ials_server_config* cfg, const float* H, ials_se
     {
         float* part = nullptr;
         SRV_TRY(hipMalloc((void**)&part, sizeof(float) * ials::gram_part_floats_needed(f.I, f.d, f.d)));
-        ials::launch_gramian_raw(s->streams[0], H, f.I, f.d, 0, f.d, f.d, part, s->G);
+        ials::launch_gramian_raw(s->streams[0], H, f.I, f.d, 0, f.d, f.d, part, s->G, false);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(s->streams[0]);
         (void)hipFree(part);

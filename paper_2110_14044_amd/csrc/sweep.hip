@@ -71,6 +71,18 @@ struct SweepArgs {
 __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// bfloat16 (round to nearest even) of four floats, packed as the 4-element operand of
+// v_mfma_f32_16x16x16_bf16 (element v stands for observation v of this lane's four).
+__device__ inline unsigned bf16_bits(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline shortx4 bf16x4(float a, float b, float c, float d) {
+    return shortx4{(short)bf16_bits(a), (short)bf16_bits(b), (short)bf16_bits(c), (short)bf16_bits(d)};
+}
+__device__ inline floatx4 mfma_bf16(shortx4 a, shortx4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
 __device__ inline float readlane(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
@@ -146,7 +158,10 @@ __device__ inline void load_cur(const SweepArgs& A, const float* X, int i, int q
 // 16t+q16, this lane group's share) += T^T (a (yhat - y)) over observations
 // [lo, hi) of one row whose own block values are own[] (block pi) and ownc[]
 // (the cache's block, TRANS only).  With TRANS the cache entries are moved to pi.
-template <int NT, bool FULL, bool TRANS>
+// BF: the Hessian products take bfloat16 operands (one 16x16x16 MFMA per tile for the
+// four observations of every lane group, 16 in all); the gradient and the predictions
+// stay float32.
+template <int NT, bool FULL, bool TRANS, bool BF>
 __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
                                   floatx4* acc, float* gp, int lane) {
     const int q16 = lane & 15, g4 = lane >> 4;
@@ -167,6 +182,7 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
         for (int st = 0; st < nsteps; st += 4) {
             const int nv = std::min(4, nsteps - st);
             float x[4][NT], xc[4][TRANS ? NT : 1];
+            float xa4[BF ? 4 : 1][NT];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (u < nv) {
@@ -206,15 +222,42 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
                         gp[t] = fmaf(rk, x[u][t], gp[t]);
                         xa[t] = ak * x[u][t];
                     }
-                    int id = 0;
+                    if constexpr (BF) {
 #pragma unroll
-                    for (int ti = 0; ti < NT; ++ti)
+                        for (int t = 0; t < NT; ++t) xa4[u][t] = xa[t];
+                    } else {
+                        int id = 0;
 #pragma unroll
-                        for (int tj = 0; tj <= ti; ++tj) {
-                            acc[id] = mfma4(xa[ti], x[u][tj], acc[id]);
-                            ++id;
-                        }
+                        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj <= ti; ++tj) {
+                                acc[id] = mfma4(xa[ti], x[u][tj], acc[id]);
+                                ++id;
+                            }
+                    }
+                } else if constexpr (BF) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        x[u][t] = 0.f;
+                        xa4[u][t] = 0.f;
+                    }
                 }
+            }
+            if constexpr (BF) {
+                shortx4 pa[NT], pb[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    pa[t] = bf16x4(xa4[0][t], xa4[1][t], xa4[2][t], xa4[3][t]);
+                    pb[t] = bf16x4(x[0][t], x[1][t], x[2][t], x[3][t]);
+                }
+                int id = 0;
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj <= ti; ++tj) {
+                        acc[id] = mfma_bf16(pa[ti], pb[tj], acc[id]);
+                        ++id;
+                    }
             }
         }
     }
@@ -228,7 +271,7 @@ __device__ inline void load_own(const SweepArgs& A, int r, int q16, float* own, 
     if constexpr (TRANS) load_cur<NT>(A, A.X, r, q16, ownc);
 }
 
-template <int NT, bool FULL, bool TRANS>
+template <int NT, bool FULL, bool TRANS, bool BF>
 __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
     constexpr int NTL = ntiles<NT>();
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
@@ -240,7 +283,7 @@ __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) gp[t] = 0.f;
         load_own<NT, FULL, TRANS>(A, A.seg_row[it], q16, own, ownc);
-        accumulate<NT, FULL, TRANS>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
+        accumulate<NT, FULL, TRANS, BF>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             gp[t] += __shfl_xor(gp[t], 16);
@@ -282,7 +325,7 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
     dtiles[e] = Dmat[colmap<NT, FULL>(16 * ti + 4 * (lq >> 4) + j) * B + colmap<NT, FULL>(16 * tj + (lq & 15))];
 }
 
-template <int NT, bool FULL, bool TRANS, bool STATIC>
+template <int NT, bool FULL, bool TRANS, bool STATIC, bool BF>
 __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
@@ -309,7 +352,7 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         if (sf < 0) {
             float own[NT], ownc[TRANS ? NT : 1];
             load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
-            accumulate<NT, FULL, TRANS>(A, lo, hi, own, ownc, acc, gp, lane);
+            accumulate<NT, FULL, TRANS, BF>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
@@ -561,13 +604,13 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
     }
 }
 
-template <int NT, bool FULL, bool TRANS>
+template <int NT, bool FULL, bool TRANS, bool BF>
 void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
     hipStream_t st = c->stream;
     const unsigned max_blocks = (unsigned)c->num_cu * 8;
     if (s.nseg > 0) {
         ProfScope ps(c, IALS_K_SEG_USER + sd);
-        hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
+        hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS, BF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
                            dim3(256), 0, st, args);
     }
     if (s.nrows > 0) {
@@ -581,17 +624,17 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
                 static int resident = 0;
                 if (resident == 0) {
                     int nb = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS, true>, 256,
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS, true, BF>, 256,
                                                                      lds) != hipSuccess ||
                         nb < 1)
                         nb = 2;
                     resident = nb;
                 }
-                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true>),
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true, BF>),
                                    dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
                                    dim3(256), lds, st, args);
             } else {
-                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, false>),
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, false, BF>),
                                    dim3(std::min<unsigned>(max_blocks, (s.nrows + 3) / 4)), dim3(256), lds, st, args);
             }
         }
@@ -607,20 +650,30 @@ bool vec_ok(const SweepArgs& A, int p0, int bw, const float* X) {
     return bw == B && (A.d % NT == 0) && (p0 % NT == 0) && ((reinterpret_cast<uintptr_t>(X) % (4 * NT)) == 0);
 }
 
-template <int NT>
+template <int NT, bool BF>
 void launch_sweep_b(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
     const bool full = vec_ok<NT>(A, A.p0, A.bw, A.Xo) && vec_ok<NT>(A, A.p0, A.bw, A.X);
     A.cur_full = vec_ok<NT>(A, A.pc, A.bwc, A.Xo) && vec_ok<NT>(A, A.pc, A.bwc, A.X);
     if (full) {
         if (trans)
-            launch_sweep_nt<NT, true, true>(c, A, s, sd);
+            launch_sweep_nt<NT, true, true, BF>(c, A, s, sd);
         else
-            launch_sweep_nt<NT, true, false>(c, A, s, sd);
+            launch_sweep_nt<NT, true, false, BF>(c, A, s, sd);
     } else {
         if (trans)
-            launch_sweep_nt<NT, false, true>(c, A, s, sd);
+            launch_sweep_nt<NT, false, true, BF>(c, A, s, sd);
         else
-            launch_sweep_nt<NT, false, false>(c, A, s, sd);
+            launch_sweep_nt<NT, false, false, BF>(c, A, s, sd);
+    }
+}
+
+template <bool BF>
+void launch_sweep_prec(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
+    switch (c->B) {
+        case 16: launch_sweep_b<1, BF>(c, A, s, sd, trans); break;
+        case 32: launch_sweep_b<2, BF>(c, A, s, sd, trans); break;
+        case 48: launch_sweep_b<3, BF>(c, A, s, sd, trans); break;
+        default: launch_sweep_b<4, BF>(c, A, s, sd, trans); break;
     }
 }
 
@@ -667,12 +720,10 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     const int64_t avg = s.nrows > 0 ? c->nnz / s.nrows : 0;
     A.rows_batch = avg < 256 ? 0 : 1;
     const bool trans = blk != c->cur_block;
-    switch (c->B) {
-        case 16: launch_sweep_b<1>(c, A, s, sd, trans); break;
-        case 32: launch_sweep_b<2>(c, A, s, sd, trans); break;
-        case 48: launch_sweep_b<3>(c, A, s, sd, trans); break;
-        default: launch_sweep_b<4>(c, A, s, sd, trans); break;
-    }
+    if (c->precision == IALS_PREC_BF16)
+        launch_sweep_prec<true>(c, A, s, sd, trans);
+    else
+        launch_sweep_prec<false>(c, A, s, sd, trans);
     c->cur_block = blk;
 }
 

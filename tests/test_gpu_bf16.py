@@ -1,0 +1,106 @@
+"""The bfloat16 precision form through the C ABI against the FP64 oracle.
+
+In this form the gathered Hessian products and the Gramian partial products
+take bfloat16 operands on the matrix cores (float32 accumulation); gradients,
+predictions, solves and updates stay float32, and the Gramian partials are
+reduced in float64.  Bars (stated per result, looser than float32): embeddings
+within 3e-2 relative (Frobenius) of the float64 oracle after the first epoch,
+and the loss within 1e-3 relative at every epoch.  The measured errors are
+printed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2110_14044_amd import binding
+from tests.gpu_util import gpu_trainer, host, need_gpu, oracle_setup, rel, say
+
+pytestmark = pytest.mark.gpu
+BF16 = binding.IALS_PREC_BF16
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _bf16_epochs(p, epochs, **kw):
+    tr = gpu_trainer(p, precision=BF16, **kw)
+    csr, ys, as_ = oracle_setup(p)
+    W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, epochs, ys, as_)
+    gl = []
+    for t in range(epochs):
+        tr.epoch(1)
+        gl.append(tr.loss()[0])
+        if t == 0:
+            W1, H1, _, _ = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1, ys, as_)
+            ew, eh = rel(host(tr.W), W1), rel(host(tr.H), H1)
+    el = [abs(a - b) / abs(b) for a, b in zip(gl, losses)]
+    say(f"{p.name} bf16 d={p.dim} b={p.block}: epoch 1 W {ew:.2e} H {eh:.2e}; loss per epoch "
+        + " ".join(f"{e:.1e}" for e in el))
+    st = tr.stats()
+    tr.close()
+    return ew, eh, el, st
+
+
+def test_bf16_tiny_four_epochs():
+    ew, eh, el, _ = _bf16_epochs(synth.make_problem("tiny"), 4)
+    assert ew < 3e-2 and eh < 3e-2
+    assert max(el) < 1e-3
+
+
+@pytest.mark.parametrize("d,b", [(64, 64), (40, 16), (48, 48), (128, 64)])
+def test_bf16_block_shapes_and_labels(d, b):
+    p = synth.small_problem(200 + d + b, 600, 400, 9000, d, b, labels=True, std=0.1)
+    ew, eh, el, _ = _bf16_epochs(p, 2)
+    assert ew < 3e-2 and eh < 3e-2
+    assert max(el) < 1e-3
+
+
+def test_bf16_long_rows_in_segments():
+    p = synth.small_problem(210, 3000, 120, 60_000, 64, 32, labels=True, zipf_s=0.8, std=0.1)
+    ew, eh, el, st = _bf16_epochs(p, 1)
+    assert st["segments_item"] > 0
+    assert ew < 3e-2 and eh < 3e-2 and max(el) < 1e-3
+
+
+def test_bf16_gramian():
+    p = synth.small_problem(220, 3000, 500, 20_000, 128, 64, std=0.1)
+    tr = gpu_trainer(p, precision=BF16)
+    for which, X in ((0, p.W0), (1, p.H0)):
+        G = host(tr.gramian(which, -1))
+        e = rel(G, oracle.gramian(X))
+        say(f"bf16 full Gramian {which}: {e:.2e}")
+        assert e < 1e-2
+    tr.close()
+
+
+def test_bf16_bitwise_deterministic():
+    p = synth.small_problem(230, 2000, 100, 40_000, 64, 32, zipf_s=0.9, std=0.1)
+    outs = []
+    for _ in range(2):
+        tr = gpu_trainer(p, precision=BF16)
+        tr.epoch(2)
+        outs.append((host(tr.W), host(tr.H), tr.predictions()))
+        tr.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_bf16_ml20m_like_epoch1():
+    """Full ML20M-shaped workload (d = 128, b = 64) in the bfloat16 form: one epoch."""
+    import time
+    p = synth.make_problem("ml20m_like")
+    tr = gpu_trainer(p, precision=BF16)
+    tr.epoch(1)
+    L1, _ = tr.loss()
+    Wg, Hg = host(tr.W), host(tr.H)
+    tr.close()
+    csr, _, _ = oracle_setup(p)
+    t = time.time()
+    W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1)
+    say(f"oracle epoch {time.time() - t:.1f}s")
+    ew, eh, el = rel(Wg, W), rel(Hg, H), abs(L1 - losses[0]) / losses[0]
+    say(f"ml20m_like bf16 epoch 1: W {ew:.2e} H {eh:.2e} loss {el:.2e}")
+    assert ew < 3e-2 and eh < 3e-2 and el < 1e-3
