@@ -124,8 +124,8 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     }
     *out = nullptr;
     if (cfg->num_users < 1 || cfg->num_items < 1 || cfg->dim < 1 || cfg->block < 1 || cfg->block > cfg->dim ||
-        cfg->block > 64) {
-        g_create_error = "need num_users >= 1, num_items >= 1, dim >= 1 and 1 <= block <= min(dim, 64)";
+        cfg->block > 256) {
+        g_create_error = "need num_users >= 1, num_items >= 1, dim >= 1 and 1 <= block <= min(dim, 256)";
         return IALS_E_INVALID;
     }
     if (!(cfg->alpha0 >= 0.f) || !(cfg->lambda > 0.f) || !std::isfinite(cfg->alpha0) || !std::isfinite(cfg->lambda)) {
@@ -161,7 +161,8 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->I = cfg->num_items;
     c->d = cfg->dim;
     c->b = cfg->block;
-    c->B = (cfg->block + 15) / 16 * 16;
+    // padded block: a multiple of 16 up to 64; 128 or 256 for the wide-block kernels
+    c->B = cfg->block <= 64 ? (cfg->block + 15) / 16 * 16 : (cfg->block <= 128 ? 128 : 256);
     c->alpha0 = cfg->alpha0;
     c->lambda = cfg->lambda;
     c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-6f;
@@ -257,6 +258,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     TRY_ALLOC(c, c->gram_part, sizeof(float) * gp);
     const int64_t nseg = std::max(us.nseg, is.nseg);
     if (nseg > 0) TRY_ALLOC(c, c->seg_part, sizeof(float) * nseg * ials::seg_part_floats_per_segment(c->B));
+    if (c->B > 64) TRY_ALLOC(c, c->fb_scratch, sizeof(double) * ials::big_fallback_doubles(c->B));
     // loss scratch: one double per user, then float64 Gramian partials (<= 256 MB)
     const size_t dd = (size_t)c->d * c->d;
     const size_t chunks = std::max<size_t>(1, std::min<size_t>(64, ((size_t)32 << 20) / dd));
@@ -532,6 +534,7 @@ ials_status ials_foldin(ials_ctx* c, int32_t n_req, const int64_t* req_ptr, cons
         if (req_ptr[r + 1] < req_ptr[r] || req_ptr[r + 1] - req_ptr[r] > (int64_t)INT32_MAX)
             return fail(c, IALS_E_INVALID, "req_ptr must be non-decreasing with requests below 2^31 items");
     if (req_ptr[n_req] > 0 && !items) return fail(c, IALS_E_INVALID, "null items");
+    if (c->b > 64) return fail(c, IALS_E_INVALID, "fold-in needs block <= 64");
     if (c->fold_G_passes != c->passes) {
         ials::launch_gramian_slab(c, c->H, c->I, 0, c->d, c->d, c->fold_G, false);
         c->fold_G_passes = c->passes;

@@ -243,14 +243,15 @@ __global__ void k_make_dmat(const float* __restrict__ G, int32_t B, int32_t p0, 
 }
 
 // R0[r][q] = alpha0 * sum_f X[r][f] G[f][q] + lambda * X[r][p0+q] (0 on padding columns).
-// One wavefront per 64 rows (4 row tiles) x B columns (NT tiles).
+// One wavefront per 64 rows (4 row tiles) x 16*NT columns (NT tiles) starting at column
+// 16*NT*blockIdx.y; G and R0 have B columns.
 template <int NT>
-__global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, const float* __restrict__ X,
+__global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
                                                const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
                                                float lambda, float* __restrict__ R0) {
-    constexpr int B = 16 * NT;
     const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int qb = 16 * NT * blockIdx.y;
     const int64_t r0 = (int64_t)wave * 64;
     if (r0 >= n) return;
     floatx4 acc[4][NT];
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, const float
             a[rt] = (fv && r < n) ? X[(size_t)r * d + ff] : 0.f;
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = fv ? G[(size_t)ff * B + 16 * t + q16] : 0.f;
+        for (int t = 0; t < NT; ++t) b[t] = fv ? G[(size_t)ff * B + qb + 16 * t + q16] : 0.f;
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, const float
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t r = r0 + 16 * rt + 4 * g4 + j;
-                const int q = 16 * t + q16;
+                const int q = qb + 16 * t + q16;
                 if (r < n)
                     R0[(size_t)r * B + q] =
                         (q < bw) ? fmaf(alpha0, acc[rt][t][j], lambda * X[(size_t)r * d + p0 + q]) : 0.f;
@@ -465,24 +466,17 @@ void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int
 void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw) {
     if (n == 0) return;
     const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
-    switch (c->B) {
-        case 16:
-            hipLaunchKernelGGL(k_dense<1>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
-                               c->lambda, c->R0);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_dense<2>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
-                               c->lambda, c->R0);
-            break;
-        case 48:
-            hipLaunchKernelGGL(k_dense<3>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
-                               c->lambda, c->R0);
-            break;
-        default:
-            hipLaunchKernelGGL(k_dense<4>, dim3(grid), dim3(256), 0, c->stream, n, c->d, X, c->G, p0, bw, c->alpha0,
-                               c->lambda, c->R0);
-            break;
+    const int B = c->B;
+#define IALS_DENSE(NTV, GY)                                                                                      \
+    hipLaunchKernelGGL(k_dense<NTV>, dim3(grid, GY), dim3(256), 0, c->stream, n, c->d, B, X, c->G, p0, bw,       \
+                       c->alpha0, c->lambda, c->R0)
+    switch (B) {
+        case 16: IALS_DENSE(1, 1); break;
+        case 32: IALS_DENSE(2, 1); break;
+        case 48: IALS_DENSE(3, 1); break;
+        default: IALS_DENSE(4, (unsigned)(B / 64)); break;
     }
+#undef IALS_DENSE
 }
 
 ials_status launch_loss(ials_ctx* c) {

@@ -48,6 +48,37 @@ struct SideIndex {
     int64_t max_len = 0;
 };
 
+// Arguments of the block-pass kernels (one pass: one side, one block pi = [p0, p0+bw)).
+struct SweepArgs {
+    const int64_t* ptr;
+    const int32_t* col;
+    const int32_t* slot;  // cache position per observation (null: identity)
+    const float* y;       // labels in this side's order (null: ones)
+    const float* a;       // weights in this side's order (null: ones)
+    float* X;             // side being updated, N x d
+    const float* Xo;      // fixed side
+    float* cache;         // prediction cache (user-major positions)
+    const float* R0;      // N x B
+    const float* Dmat;    // B x B
+    float* dtiles;        // the Hessian start in accumulator layout (NTL x 64 x 4)
+    int32_t d, p0, bw, nrows;
+    int32_t pc, bwc;      // the block the cache is relative to when the pass starts
+    int32_t cur_full;     // that block is loaded with vector loads
+    const int32_t* order;
+    const int32_t* seg_first;
+    const int32_t* seg_row;
+    const int64_t* seg_lo;
+    const int64_t* seg_hi;
+    int32_t nseg;
+    float* seg_part;
+    int32_t* fb_list;
+    int32_t* cursors;
+    unsigned long long* counters;
+    float tau;
+    int32_t rows_batch;   // 0: static round-robin rows; 1: rows from the shared queue
+    double* fb_scratch;   // float64 Hessians of the wide-block fallback (one B x B per workgroup)
+};
+
 // One fold-in request as the fold-in kernel reads it (from device or pinned host memory).
 struct FoldReq {
     const int32_t* items;  // [n] item ids
@@ -98,6 +129,7 @@ struct ials_ctx {
     float* gram_part = nullptr;  // split-K partials
     size_t gram_part_floats = 0;
     float* seg_part = nullptr;   // per-segment partial Hessian + gradient
+    double* fb_scratch = nullptr;  // float64 fallback Hessians when B > 64
     int32_t* fb_list = nullptr;  // [max(U,I)]
     int32_t* cursors = nullptr;  // [CUR_NUM]
     unsigned long long* counters = nullptr;  // [CNT_NUM]
@@ -165,6 +197,8 @@ void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int
                          float* out, bool make_dmat);
 void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw);
 void launch_sweep(ials_ctx* c, int side, int32_t blk);
+// The pass for blocks wider than 64 coordinates (B = 128 or 256).
+void launch_sweep_big(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans);
 ials_status launch_loss(ials_ctx* c);
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
 // out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats);
@@ -177,6 +211,7 @@ size_t fold_ws_floats(const FoldShape& f, int64_t n);
 hipError_t launch_foldin(hipStream_t st, const FoldShape& f, const float* H, const float* G, float alpha0,
                          float lambda, float tau, int32_t passes, const FoldReq* reqs, int32_t m, int32_t* counters);
 size_t seg_part_floats_per_segment(int32_t B);
+size_t big_fallback_doubles(int32_t B);
 
 // Allocation helper that tracks the context's byte count and budget.
 hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes);

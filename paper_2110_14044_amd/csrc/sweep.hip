@@ -39,34 +39,7 @@
 namespace ials {
 namespace {
 
-struct SweepArgs {
-    const int64_t* ptr;
-    const int32_t* col;
-    const int32_t* slot;  // cache position per observation (null: identity)
-    const float* y;       // labels in this side's order (null: ones)
-    const float* a;       // weights in this side's order (null: ones)
-    float* X;             // side being updated, N x d
-    const float* Xo;      // fixed side
-    float* cache;         // prediction cache (user-major positions)
-    const float* R0;      // N x B
-    const float* Dmat;    // B x B
-    float* dtiles;        // the Hessian start in accumulator layout (NTL x 64 x 4)
-    int32_t d, p0, bw, nrows;
-    int32_t pc, bwc;      // the block the cache is relative to when the pass starts
-    int32_t cur_full;     // that block is loaded with vector loads
-    const int32_t* order;
-    const int32_t* seg_first;
-    const int32_t* seg_row;
-    const int64_t* seg_lo;
-    const int64_t* seg_hi;
-    int32_t nseg;
-    float* seg_part;
-    int32_t* fb_list;
-    int32_t* cursors;
-    unsigned long long* counters;
-    float tau;
-    int32_t rows_batch;   // 0: static round-robin rows; 1: rows from the shared queue
-};
+
 
 __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -720,7 +693,9 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     const int64_t avg = s.nrows > 0 ? c->nnz / s.nrows : 0;
     A.rows_batch = avg < 256 ? 0 : 1;
     const bool trans = blk != c->cur_block;
-    if (c->precision == IALS_PREC_BF16)
+    if (c->B > 64)
+        launch_sweep_big(c, A, s, sd, trans);
+    else if (c->precision == IALS_PREC_BF16)
         launch_sweep_prec<true>(c, A, s, sd, trans);
     else
         launch_sweep_prec<false>(c, A, s, sd, trans);

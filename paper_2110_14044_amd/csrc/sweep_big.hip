@@ -1,0 +1,653 @@
+// The block pass of iALS++ (sec. 4, eq. 8-9, Alg. 3) for blocks wider than 64
+// coordinates: B = 128 (NT = 8 tiles of 16) or B = 256 (NT = 16).
+//
+// One workgroup of NT/2 wavefronts per row.  Wave w owns the lower tiles of the
+// two tile rows w and NT-1-w (NT+1 tiles, the same count for every wave).
+//
+// Accumulation: every wave walks the row's observations; per observation it
+// gathers the partner's block (lane q16 of group g4 takes columns 16t + q16),
+// forms the prediction from the cache and the row's own block, and adds
+// a_k x x^T into its own tiles on the matrix cores (float32 16x16x4 per four
+// observations, or bfloat16 16x16x16 per sixteen).  Wave 0 also accumulates the
+// gradient and moves the cache.  Rows longer than kSegLen observations take
+// per-segment partials instead (k_seg_big), summed in segment order.
+//
+// Factorisation: the tiles go to LDS (packed lower tiles, 256 floats each) and a
+// right-looking blocked Cholesky runs over them with rolled loops (the code stays
+// small): for panel K every wave factors and inverts the 16 x 16 diagonal tile
+// itself (Y = L_KK^-1) and forward-substitutes z_K = L_KK^-1 g_K; the owner of
+// each tile row I > K forms L_IK = A_IK Y^T on the matrix cores and updates g_I;
+// after a barrier every owner subtracts L_IK L_JK^T from its tiles (I, J), K < J <= I.
+// Back substitution L^T x = z goes panel by panel from the last: the owners'
+// partial sums L_IK^T x_I meet in LDS (one barrier per panel) and every wave forms
+// x_K = Y_KK^T (z_K - sum) itself.  A row whose pivots fail the ratio test is redone
+// in float64 by k_fallback_big.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ials_internal.h"
+
+namespace ials {
+namespace {
+
+__device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 mfma_bf16(shortx4 a, shortx4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline short bf16s(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float readlane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ inline float sum16(float s) {
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    return s;
+}
+__device__ inline void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ inline int tile_id(int I, int J) { return I * (I + 1) / 2 + J; }
+
+template <int NT>
+struct BigLds {
+    static constexpr int B = 16 * NT, NW = NT / 2, NTL = NT * (NT + 1) / 2;
+    static constexpr int MAT = 0;                 // NTL packed lower tiles, row-major 16 x 16
+    static constexpr int YP = MAT + NTL * 256;    // [NW][256] each wave's copy of Y_KK
+    static constexpr int XW = YP + NW * 256;      // [NW][B]   each wave's copy of the solution
+    static constexpr int G = XW + NW * B;         // [B]       gradient, then z = L^-1 g
+    static constexpr int SP = G + B;              // [2][NW][16] back-substitution partials
+    static constexpr int OWN = SP + 2 * NW * 16;  // [2][B] the row's own values (pass block, cache block)
+    static constexpr int TOTAL = OWN + 2 * B;
+};
+
+// x[t] = X[i][p0 + 16t + q16] (0 outside the block)
+template <int NT>
+__device__ inline void load_block(const float* __restrict__ X, int d, int i, int p0, int bw, int q16, float* x) {
+    const float* xr = X + (size_t)i * d + p0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = 16 * t + q16;
+        const float v = xr[c < bw ? c : 0];
+        x[t] = c < bw ? v : 0.f;
+    }
+}
+template <int NT>
+__device__ inline float pick(const float* x, int I) {
+    float r = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) r = (t == I) ? x[t] : r;
+    return r;
+}
+
+// The wave's NT+1 tiles: m <= I1 is tile (I1, m); m > I1 is tile (I2, m - I1 - 1), I2 = NT-1-I1.
+__device__ inline void tile_of(int m, int I1, int NT, int& I, int& J) {
+    if (m <= I1) {
+        I = I1;
+        J = m;
+    } else {
+        I = NT - 1 - I1;
+        J = m - I1 - 1;
+    }
+}
+
+// own / ownc: the row's values at this pass's block and at the cache's block (LDS, by column).
+// acc[m] (the wave's tiles) += sum_k a_k x_k x_k^T over observations [lo, hi); the lead
+// wave also accumulates gp[t] += sum_k a_k (yhat_k - y_k) x_k[t] and, with TRANS, moves
+// the cache entries to this pass's block.  The gathered values go through this wave's
+// LDS staging area (NT x 64 floats, or NT x 64 packed bfloat16 quadruples) so that a
+// tile's column operand is addressed by its index.
+template <int NT, bool TRANS, bool BF>
+__device__ void big_accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
+                               int I1, floatx4* acc, float* gp, bool lead, int lane, float* stage) {
+    const int q16 = lane & 15, g4 = lane >> 4;
+    const int I2 = NT - 1 - I1;
+    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+        const int64_t k = c0 + lane;
+        const bool v = k < hi;
+        int ci = 0, si = 0;
+        float cv = 0.f, yv = 1.f, av = 1.f;
+        if (v) {
+            ci = A.col[k];
+            si = A.slot ? A.slot[k] : (int)k;
+            cv = A.cache[si];
+            if (A.y) yv = A.y[k];
+            if (A.a) av = A.a[k];
+        }
+        const int cnt = (int)std::min<int64_t>(64, hi - c0);
+        const int nsteps = (cnt + 3) >> 2;
+        for (int st = 0; st < nsteps; st += 4) {
+            shortx4 pa1{0, 0, 0, 0}, pa2{0, 0, 0, 0}, pb[BF ? NT : 1];
+            if constexpr (BF) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) pb[t] = shortx4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (st + u >= nsteps) break;
+                float x[NT];
+                const int src = 4 * (st + u) + g4;
+                const bool valid = src < cnt;
+                const int i = __shfl(ci, src);
+                load_block<NT>(A.Xo, A.d, i, A.p0, A.bw, q16, x);
+                const float ck = __shfl(cv, src);
+                const float yk = A.y ? __shfl(yv, src) : 1.f;
+                const float ak_all = A.a ? __shfl(av, src) : 1.f;
+                const float ak = valid ? ak_all : 0.f;
+                float sp = 0.f;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) sp = fmaf(x[t], own[16 * t + q16], sp);
+                sp = sum16(sp);
+                float yh = ck + sp;
+                if constexpr (TRANS) {
+                    float xc[NT];
+                    load_block<NT>(A.Xo, A.d, i, A.pc, A.bwc, q16, xc);
+                    float sc = 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) sc = fmaf(xc[t], ownc[16 * t + q16], sc);
+                    sc = sum16(sc);
+                    yh = ck + sc;
+                    const int sk = __shfl(si, src);
+                    if (lead && q16 == 0 && valid) A.cache[sk] = yh - sp;
+                }
+                const float rk = ak * (yh - yk);
+                if (lead) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) gp[t] = fmaf(rk, x[t], gp[t]);
+                }
+                const float xa1 = ak * pick<NT>(x, I1);
+                const float xa2 = ak * pick<NT>(x, I2);
+                if constexpr (BF) {
+                    pa1[u] = bf16s(xa1);
+                    pa2[u] = bf16s(xa2);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) pb[t][u] = bf16s(x[t]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) stage[t * 64 + lane] = x[t];
+                    wave_fence();
+#pragma unroll
+                    for (int m = 0; m <= NT; ++m) {
+                        const int J = m <= I1 ? m : m - I1 - 1;
+                        acc[m] = mfma4(m <= I1 ? xa1 : xa2, stage[J * 64 + lane], acc[m]);
+                    }
+                    wave_fence();
+                }
+            }
+            if constexpr (BF) {
+                shortx4* st4 = reinterpret_cast<shortx4*>(stage);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) st4[t * 64 + lane] = pb[t];
+                wave_fence();
+#pragma unroll
+                for (int m = 0; m <= NT; ++m) {
+                    const int J = m <= I1 ? m : m - I1 - 1;
+                    acc[m] = mfma_bf16(m <= I1 ? pa1 : pa2, st4[J * 64 + lane], acc[m]);
+                }
+                wave_fence();
+            }
+        }
+    }
+}
+
+// floats of one segment partial: NTL tiles in accumulator layout + B gradient entries
+template <int NT>
+constexpr int big_seg_stride() { return NT * (NT + 1) / 2 * 256 + 16 * NT; }
+
+// the row's own block values (this pass's block and the cache's block) into LDS
+template <int NT, bool TRANS>
+__device__ inline void own_to_lds(const SweepArgs& A, int r, float* own, float* ownc) {
+    constexpr int B = 16 * NT;
+    for (int q = threadIdx.x; q < B; q += blockDim.x) {
+        own[q] = q < A.bw ? A.X[(size_t)r * A.d + A.p0 + q] : 0.f;
+        if constexpr (TRANS) ownc[q] = q < A.bwc ? A.X[(size_t)r * A.d + A.pc + q] : 0.f;
+    }
+}
+
+template <int NT, bool TRANS, bool BF>
+__global__ __launch_bounds__(NT * 32) void k_seg_big(SweepArgs A) {
+    __shared__ __align__(16) float stage_all[NT / 2][NT * 128];
+    __shared__ float own[16 * NT], ownc[16 * NT];
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int I1 = wave;
+    const bool lead = wave == 0;
+    for (int it = blockIdx.x; it < A.nseg; it += gridDim.x) {
+        floatx4 acc[NT + 1];
+        float gp[NT];
+#pragma unroll
+        for (int m = 0; m <= NT; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) gp[t] = 0.f;
+        const int r = A.seg_row[it];
+        __syncthreads();  // the previous segment's readers are done with own / ownc
+        own_to_lds<NT, TRANS>(A, r, own, ownc);
+        __syncthreads();
+        big_accumulate<NT, TRANS, BF>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, I1, acc, gp, lead, lane,
+                                      stage_all[wave]);
+        float* P = A.seg_part + (size_t)it * big_seg_stride<NT>();
+#pragma unroll
+        for (int m = 0; m <= NT; ++m) {
+            int I, J;
+            tile_of(m, I1, NT, I, J);
+            *reinterpret_cast<floatx4*>(P + ((size_t)tile_id(I, J) * 64 + lane) * 4) = acc[m];
+        }
+        if (lead) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                gp[t] += __shfl_xor(gp[t], 16);
+                gp[t] += __shfl_xor(gp[t], 32);
+            }
+            if (g4 == 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) P[NT * (NT + 1) / 2 * 256 + 16 * t + q16] = gp[t];
+            }
+        }
+    }
+}
+
+// tile (accumulator layout: lane l, register j = element (4(l/16)+j, l%16)) <-> LDS row-major
+__device__ inline void tile_store(float* T, floatx4 c, int lane) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) T[(4 * (lane >> 4) + j) * 16 + (lane & 15)] = c[j];
+}
+__device__ inline floatx4 tile_load(const float* T, int lane) {
+    floatx4 c;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = T[(4 * (lane >> 4) + j) * 16 + (lane & 15)];
+    return c;
+}
+// c += sgn * P Q^T for 16 x 16 row-major tiles P, Q
+__device__ inline floatx4 mm_pqt(floatx4 c, const float* P, const float* Q, float sgn, int lane) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int o = (lane & 15) * 16 + 4 * s + (lane >> 4);
+        c = mfma4(sgn * P[o], Q[o], c);
+    }
+    return c;
+}
+
+template <int NT, bool TRANS, bool BF>
+__global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
+    using L = BigLds<NT>;
+    constexpr int B = L::B, NW = L::NW, NTL = L::NTL;
+    extern __shared__ __align__(16) float lds_big[];
+    const int lane0 = threadIdx.x & 63;
+    const int wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    static_assert(BigLds<NT>::NW * NT * 128 <= BigLds<NT>::NTL * 256, "staging fits in the matrix region");
+    float* mat = lds_big + L::MAT;
+    float* gl = lds_big + L::G;
+    float* spart = lds_big + L::SP;
+
+    for (int it = blockIdx.x; it < A.nrows; it += gridDim.x) {
+        const int r = A.order[it];
+        const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
+        // The lane and wave ids are laundered per row so that the row-invariant addresses
+        // derived from them are formed inside the row, not hoisted out of the row loop
+        // into registers for the whole kernel.
+        int lane = lane0, I1 = wave0;
+        asm volatile("" : "+v"(lane));
+        asm volatile("" : "+s"(I1));
+        const int q16 = lane & 15, g4 = lane >> 4, I2 = NT - 1 - I1;
+        const bool lead = I1 == 0;
+        float* yp = lds_big + L::YP + I1 * 256;
+        float* xw = lds_big + L::XW + I1 * B;
+        floatx4 acc[NT + 1];
+        float gp[NT];
+        const float* Dm = A.Dmat;
+        // the Hessian starts from alpha0 G_pipi + lambda I
+#pragma unroll
+        for (int m = 0; m <= NT; ++m) {
+            int I, J;
+            tile_of(m, I1, NT, I, J);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[m][j] = Dm[(size_t)(16 * I + 4 * g4 + j) * B + 16 * J + q16];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) gp[t] = 0.f;
+        const int sf = A.seg_first[r];
+        if (sf < 0) {
+            float* own = lds_big + L::OWN;
+            own_to_lds<NT, TRANS>(A, r, own, own + B);
+            __syncthreads();
+            // staging aliases the matrix region, which is not in use yet
+            big_accumulate<NT, TRANS, BF>(A, lo, hi, own, own + B, I1, acc, gp, lead, lane, mat + I1 * NT * 128);
+            if (lead) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    gp[t] += __shfl_xor(gp[t], 16);
+                    gp[t] += __shfl_xor(gp[t], 32);
+                }
+            }
+        } else {
+            const int ns = (int)((hi - lo + kSegLen - 1) / kSegLen);
+            for (int s = sf; s < sf + ns; ++s) {
+                const float* P = A.seg_part + (size_t)s * big_seg_stride<NT>();
+#pragma unroll
+                for (int m = 0; m <= NT; ++m) {
+                    int I, J;
+                    tile_of(m, I1, NT, I, J);
+                    acc[m] += *reinterpret_cast<const floatx4*>(P + ((size_t)tile_id(I, J) * 64 + lane) * 4);
+                }
+                if (lead) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) gp[t] += P[NTL * 256 + 16 * t + q16];
+                }
+            }
+        }
+        if (lead && g4 == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) gl[16 * t + q16] = gp[t] + A.R0[(size_t)r * B + 16 * t + q16];
+        }
+        __syncthreads();  // every wave is done with its staging before the tiles land on it
+#pragma unroll
+        for (int m = 0; m <= NT; ++m) {
+            int I, J;
+            tile_of(m, I1, NT, I, J);
+            tile_store(mat + tile_id(I, J) * 256, acc[m], lane);
+        }
+        __syncthreads();
+
+        // blocked Cholesky with the forward substitution folded in
+        float pmin = 3.0e38f, pmax = 0.f;
+        const int i16 = lane & 15;
+#pragma unroll 1
+        for (int K = 0; K < NT; ++K) {
+            float* TK = mat + tile_id(K, K) * 256;
+            float a[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) a[k] = TK[i16 * 16 + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float piv = readlane(a[k], k);
+                if (16 * K + k < A.bw) {
+                    pmin = fminf(pmin, piv);
+                    pmax = fmaxf(pmax, piv);
+                }
+                const float rs = piv > 0.f ? __builtin_amdgcn_rsqf(piv) : 0.f;
+                const float l = a[k] * rs;
+                a[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < 16; ++j) a[j] = fmaf(-l, readlane(l, j), a[j]);
+            }
+            // Y = L_KK^-1, lane j holding column j
+            float y[16];
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) {
+                float s = 0.f;
+#pragma unroll
+                for (int k = 0; k < ii; ++k) s = fmaf(readlane(a[k], ii), y[k], s);
+                const float di = 1.f / readlane(a[ii], ii);
+                y[ii] = (ii < i16) ? 0.f : (ii == i16 ? di : -s * di);
+            }
+            // z_K = L_KK^-1 g_K, lane i holding z_i
+            float zi = gl[16 * K + i16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float zk = readlane(zi, k) / readlane(a[k], k);
+                zi = (i16 > k) ? fmaf(-a[k], zk, zi) : (i16 == k ? zk : zi);
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) yp[ii * 16 + lane] = y[ii];
+            }
+            wave_fence();
+            // owners of tile rows I > K: L_IK = A_IK Y^T and g_I -= L_IK z_K
+#pragma unroll 1
+            for (int pass = 0; pass < 2; ++pass) {
+                const int I = pass == 0 ? I1 : I2;
+                if (I <= K) continue;
+                float* P = mat + tile_id(I, K) * 256;
+                floatx4 c = mm_pqt(floatx4{0.f, 0.f, 0.f, 0.f}, P, yp, 1.f, lane);
+                wave_fence();
+                tile_store(P, c, lane);
+                const float zq = __shfl(zi, q16);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float s = sum16(c[j] * zq);
+                    if (q16 == 0) gl[16 * I + 4 * g4 + j] -= s;
+                }
+            }
+            __syncthreads();
+            // Y_KK and z_K are kept for the back substitution (tile (K,K) is no longer read)
+            if (lead && lane < 16) {
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) TK[ii * 16 + lane] = y[ii];
+                gl[16 * K + lane] = zi;
+            }
+            // trailing tiles: A_IJ -= L_IK L_JK^T for K < J <= I
+#pragma unroll 1
+            for (int pass = 0; pass < 2; ++pass) {
+                const int I = pass == 0 ? I1 : I2;
+                if (I <= K) continue;
+                const float* LI = mat + tile_id(I, K) * 256;
+#pragma unroll 1
+                for (int J = K + 1; J <= I; ++J) {
+                    float* T = mat + tile_id(I, J) * 256;
+                    floatx4 c = tile_load(T, lane);
+                    c = mm_pqt(c, LI, mat + tile_id(J, K) * 256, -1.f, lane);
+                    tile_store(T, c, lane);
+                }
+            }
+            __syncthreads();
+        }
+        const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < A.tau * pmax)) ? 1 : 0);
+        if (bad) {
+            if (lead && lane == 0) {
+                const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
+                A.fb_list[pos] = r;
+            }
+            __syncthreads();
+            continue;
+        }
+        // back substitution L^T x = z, panel by panel from the last
+#pragma unroll 1
+        for (int K = NT - 1; K >= 0; --K) {
+            float s = 0.f;  // lane: column q16 of tile column K, rows 4 g4 .. 4 g4 + 3
+#pragma unroll 1
+            for (int pass = 0; pass < 2; ++pass) {
+                const int I = pass == 0 ? I1 : I2;
+                if (I <= K) continue;
+                const float* P = mat + tile_id(I, K) * 256;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s = fmaf(P[(4 * g4 + j) * 16 + q16], xw[16 * I + 4 * g4 + j], s);
+            }
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            float* sp = spart + (K & 1) * NW * 16;
+            if (g4 == 0) sp[I1 * 16 + q16] = s;
+            __syncthreads();
+            // every wave: x_K = Y_KK^T (z_K - sum of the partials)
+            const float* TK = mat + tile_id(K, K) * 256;
+            float x = 0.f;
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                float t = gl[16 * K + rr];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t -= sp[w * 16 + rr];
+                x = fmaf(TK[rr * 16 + i16], t, x);
+            }
+            if (lane < 16) xw[16 * K + lane] = x;
+            wave_fence();
+        }
+        if (lead) {
+            for (int q = lane; q < A.bw; q += 64) A.X[(size_t)r * A.d + A.p0 + q] -= xw[q];
+        }
+        __syncthreads();
+    }
+}
+
+// Float64 redo of rejected rows for wide blocks: the Hessian lives in a global float64
+// scratch (one B x B per workgroup), gathered rows come through LDS in chunks of 8.
+template <int NT>
+__global__ __launch_bounds__(256) void k_fallback_big(SweepArgs A) {
+    constexpr int B = 16 * NT, CH = 8;
+    __shared__ double xs[CH][B];
+    __shared__ double gv[B], own[B];
+    __shared__ double rs[CH], ws[CH];
+    __shared__ int ok;
+    const int tid = threadIdx.x;
+    double* Hm = A.fb_scratch + (size_t)blockIdx.x * B * B;
+    const int nfb = A.cursors[CUR_FB_LIST];
+    for (int idx = blockIdx.x; idx < nfb; idx += gridDim.x) {
+        const int r = A.fb_list[idx];
+        const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
+        for (int e = tid; e < B * B; e += 256) Hm[e] = (double)A.Dmat[e];
+        if (tid < B) {
+            gv[tid] = (double)A.R0[(size_t)r * B + tid];
+            own[tid] = tid < A.bw ? (double)A.X[(size_t)r * A.d + A.p0 + tid] : 0.0;
+        }
+        if (tid == 0) ok = 1;
+        __syncthreads();
+        for (int64_t c0 = lo; c0 < hi; c0 += CH) {
+            for (int e = tid; e < CH * B; e += 256) {
+                const int j = e / B, c = e % B;
+                const int64_t k = c0 + j;
+                xs[j][c] = (k < hi && c < A.bw) ? (double)A.Xo[(size_t)A.col[k] * A.d + A.p0 + c] : 0.0;
+            }
+            __syncthreads();
+            if (tid < CH) {
+                const int64_t k = c0 + tid;
+                double res = 0.0, w = 0.0;
+                if (k < hi) {
+                    const int64_t s = A.slot ? (int64_t)A.slot[k] : k;
+                    const double ak = A.a ? (double)A.a[k] : 1.0;
+                    const double yk = A.y ? (double)A.y[k] : 1.0;
+                    double yh = (double)A.cache[s];
+                    for (int c = 0; c < A.bw; ++c) yh += own[c] * xs[tid][c];
+                    res = ak * (yh - yk);
+                    w = ak;
+                }
+                rs[tid] = res;
+                ws[tid] = w;
+            }
+            __syncthreads();
+            for (int e = tid; e < B * B; e += 256) {
+                const int p = e / B, q = e % B;
+                double s = 0.0;
+                for (int j = 0; j < CH; ++j) s += ws[j] * xs[j][p] * xs[j][q];
+                Hm[e] += s;
+            }
+            if (tid < B) {
+                double s = 0.0;
+                for (int j = 0; j < CH; ++j) s += rs[j] * xs[j][tid];
+                gv[tid] += s;
+            }
+            __syncthreads();
+        }
+        // right-looking Cholesky in float64 (lower triangle), the workgroup sharing each column
+        for (int k = 0; k < B; ++k) {
+            if (tid == 0) {
+                double v = Hm[(size_t)k * B + k];
+                if (!(v > 0.0)) {
+                    ok = 0;
+                    v = 1.0;
+                }
+                Hm[(size_t)k * B + k] = sqrt(v);
+            }
+            __syncthreads();
+            for (int i = k + 1 + tid; i < B; i += 256) Hm[(size_t)i * B + k] /= Hm[(size_t)k * B + k];
+            __syncthreads();
+            const int t = B - k - 1;
+            for (int e = tid; e < t * t; e += 256) {
+                const int i = k + 1 + e / t, j = k + 1 + e % t;
+                if (j <= i) Hm[(size_t)i * B + j] -= Hm[(size_t)i * B + k] * Hm[(size_t)j * B + k];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            for (int i = 0; i < B; ++i) {
+                double s = gv[i];
+                for (int k = 0; k < i; ++k) s -= Hm[(size_t)i * B + k] * gv[k];
+                gv[i] = s / Hm[(size_t)i * B + i];
+            }
+            for (int i = B - 1; i >= 0; --i) {
+                double s = gv[i];
+                for (int k = i + 1; k < B; ++k) s -= Hm[(size_t)k * B + i] * gv[k];
+                gv[i] = s / Hm[(size_t)i * B + i];
+            }
+            if (!ok) {
+                atomicAdd(&A.counters[CNT_NOT_SPD], 1ull);
+                for (int i = 0; i < B; ++i) gv[i] = 0.0;
+            }
+            atomicAdd(&A.counters[CNT_FALLBACK_ROWS], 1ull);
+        }
+        __syncthreads();
+        if (tid < A.bw) A.X[(size_t)r * A.d + A.p0 + tid] -= (float)gv[tid];
+        __syncthreads();
+    }
+}
+
+constexpr int kFallbackBlocksBig = 64;
+
+template <int NT, bool TRANS, bool BF>
+void launch_big_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+    using L = BigLds<NT>;
+    hipStream_t st = c->stream;
+    const unsigned threads = NT * 32;
+    if (s.nseg > 0) {
+        ProfScope ps(c, IALS_K_SEG_USER + sd);
+        hipLaunchKernelGGL((k_seg_big<NT, TRANS, BF>), dim3(std::min<unsigned>((unsigned)c->num_cu * 4, (unsigned)s.nseg)),
+                           dim3(threads), 0, st, args);
+    }
+    if (s.nrows > 0) {
+        const size_t lds = sizeof(float) * L::TOTAL;
+        static int resident = 0;
+        if (resident == 0) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows_big<NT, TRANS, BF>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rows_big<NT, TRANS, BF>, (int)threads, lds) !=
+                    hipSuccess ||
+                nb < 1)
+                nb = 1;
+            resident = nb;
+        }
+        {
+            ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
+            hipLaunchKernelGGL((k_rows_big<NT, TRANS, BF>),
+                               dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (unsigned)s.nrows)),
+                               dim3(threads), lds, st, args);
+        }
+        ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
+        hipLaunchKernelGGL((k_fallback_big<NT>), dim3(kFallbackBlocksBig), dim3(256), 0, st, args);
+    }
+}
+
+template <int NT, bool BF>
+void launch_big_b(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
+    if (trans)
+        launch_big_nt<NT, true, BF>(c, A, s, sd);
+    else
+        launch_big_nt<NT, false, BF>(c, A, s, sd);
+}
+
+}  // namespace
+
+size_t big_fallback_doubles(int32_t B) { return (size_t)kFallbackBlocksBig * B * B; }
+
+void launch_sweep_big(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
+    const bool bf = c->precision == IALS_PREC_BF16;
+    A.fb_scratch = c->fb_scratch;
+    if (c->B == 128) {
+        if (bf)
+            launch_big_b<8, true>(c, A, s, sd, trans);
+        else
+            launch_big_b<8, false>(c, A, s, sd, trans);
+    } else {
+        if (bf)
+            launch_big_b<16, true>(c, A, s, sd, trans);
+        else
+            launch_big_b<16, false>(c, A, s, sd, trans);
+    }
+}
+
+}  // namespace ials
