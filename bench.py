@@ -192,6 +192,10 @@ def main():
     ap.add_argument("--workload", default="ml20m_like")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
+    ap.add_argument("--block", type=int, default=0, help="block size b (0: the workload's)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose b, row dealing and segment length by measurement first (cached in --tune-cache)")
+    ap.add_argument("--tune-cache", default=os.path.join("gpurun_out", "autotune.json"))
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
                     help="arithmetic of the timed epochs (the bf16 form: bfloat16 Hessian and Gramian products)")
     ap.add_argument("--matched-loss-epochs", type=int, default=16,
@@ -232,10 +236,18 @@ def main():
     log(f"[bench] generating {wl.name}: {wl.num_users}x{wl.num_items}, {wl.nnz} obs, d={wl.dim} b={wl.block}")
     t0 = time.time()
     p = synth.make_problem(args.workload)
+    if args.block:
+        p.block = args.block
     log(f"[bench] generated in {time.time() - t0:.1f}s; building the index on the GPU")
     torch.cuda.set_device(0)
     prec = binding.IALS_PREC_BF16 if args.precision == "bf16" else binding.IALS_PREC_FP32
-    tr = Trainer(p, graph=not args.no_graph, precision=prec)
+    deal, seg_len, tuned = "auto", 0, None
+    if args.autotune:
+        from paper_2110_14044_amd import autotune
+        tuned = autotune.tune(p, prec, cache_path=args.tune_cache, log=log)
+        p.block, deal, seg_len = tuned["block"], tuned["deal"], tuned["seg_len"]
+        log(f"[bench] tuned: b={p.block} deal={deal} seg_len={seg_len} (estimated epoch {tuned['epoch_ms']:.1f} ms)")
+    tr = Trainer(p, graph=not args.no_graph, precision=prec, deal=deal, seg_len=seg_len)
     torch.cuda.synchronize()
     st = tr.stats()
     log(f"[bench] index built: long rows user {st['long_rows_user']} item {st['long_rows_item']}, "
@@ -283,11 +295,17 @@ def main():
     flops, bytes_ = rows_work(li if dom == "rows_item" else lu, p.block, 1.0 if dom.endswith("_move") else 0.0)
     avg_s = kern[dom]["avg_ms"] / 1e3
     achieved = flops / avg_s / 1e12
+    if p.block > 64:
+        nt = 8 if p.block <= 128 else 16
+        kname = {"rows_user": f"k_rows_big<{nt},false,.> (user pass)",
+                 "rows_user_move": f"k_rows_big<{nt},true,.> (user pass that moves the prediction cache)",
+                 "rows_item": f"k_rows_big<{nt},false,.> (item pass)"}[dom]
+    else:
+        kname = {"rows_user": "k_sweep_rows<NT,.,false,.> (user pass)",
+                 "rows_user_move": "k_sweep_rows<NT,.,true,.> (user pass that moves the prediction cache)",
+                 "rows_item": "k_sweep_rows<NT,.,false,.> (item pass)"}[dom]
     roofline = {
-        "kernel": {"rows_user": "k_sweep_rows<4,true,false,true> (user pass)",
-                   "rows_user_move": "k_sweep_rows<4,true,true,true> (user pass that moves the prediction cache)",
-                   "rows_item": "k_sweep_rows<4,true,false,false> (item pass)"}[dom]
-                  + ": gather + MFMA Hessian + blocked Cholesky + update",
+        "kernel": kname + ": gather + MFMA Hessian + blocked Cholesky + update",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(dom),
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
@@ -299,15 +317,33 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        log(f"[bench] cpu baseline: FP64 oracle, one epoch of {wl.name} on {threads} threads")
         csr = oracle.build_csr(p.num_users, p.num_items, p.user, p.item)
-        tc = time.perf_counter()
-        oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1)
-        t_cpu = time.perf_counter() - tc
-        log(f"[bench] oracle epoch {t_cpu:.2f}s")
-        cpu = {"value": nnzb / t_cpu, "unit": "nnz·b/s", "cores": threads, "kind": "oracle",
-               "sample": f"one full epoch of {wl.name} (from W0, H0; includes the per-epoch loss), "
-                         f"{t_cpu:.2f} s", "epoch_s": t_cpu}
+        nblocks = (p.dim + p.block - 1) // p.block
+        if nblocks <= 2:
+            log(f"[bench] cpu baseline: FP64 oracle, one epoch of {wl.name} on {threads} threads")
+            tc = time.perf_counter()
+            oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1)
+            t_cpu = time.perf_counter() - tc
+            sample = f"one full epoch of {wl.name} (from W0, H0; includes the per-epoch loss), {t_cpu:.2f} s"
+            work = nnzb
+        else:
+            # one block of the epoch: predictions, then the user pass and the item pass of block 0
+            log(f"[bench] cpu baseline: FP64 oracle, block 0 (both passes) of {wl.name} on {threads} threads")
+            import numpy as np
+            W = p.W0.astype(np.float64)
+            H = p.H0.astype(np.float64)
+            tc = time.perf_counter()
+            yhat = oracle.predict(csr, W, H)
+            bw = min(p.block, p.dim)
+            oracle.block_pass(csr, "user", 0, bw, p.alpha0, p.lam, W, H, yhat, oracle.gramian(H, 0, bw))
+            oracle.block_pass(csr, "item", 0, bw, p.alpha0, p.lam, W, H, yhat, oracle.gramian(W, 0, bw))
+            t_cpu = time.perf_counter() - tc
+            sample = (f"block 0 of {nblocks} of {wl.name} at b={p.block} (predictions + user pass + item pass), "
+                      f"{t_cpu:.2f} s; value = 2 |S| b / that time")
+            work = 2.0 * p.nnz * p.block
+        log(f"[bench] oracle sample {t_cpu:.2f}s")
+        cpu = {"value": work / t_cpu, "unit": "nnz·b/s", "cores": threads, "kind": "oracle", "sample": sample,
+               "seconds": t_cpu}
 
     tr.close()
     matched = None
@@ -325,8 +361,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": epoch_s * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16" else "f32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.num_users} users x {wl.num_items} items, {wl.nnz} observations "
-                               f"(y=alpha=1), d={wl.dim}, b={wl.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
-                   "epoch_s": epoch_s, "parallelism": "single GPU"},
+                               f"(y=alpha=1), d={wl.dim}, b={p.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
+                   "epoch_s": epoch_s, "parallelism": "single GPU", "deal": deal, "seg_len": seg_len or 1024},
+        "autotune": tuned,
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,
     }

@@ -67,12 +67,18 @@ typedef enum { IALS_PREC_FP32 = 0, IALS_PREC_BF16 = 1 } ials_precision;
  * is, ials_create makes a private stream for the context.  While profiling is on
  * (ials_profile_enable) epochs run launch by launch. */
 enum { IALS_FLAG_GRAPH = 1u };
+/* Row dealing of the block-pass kernels (tuning; results do not depend on it):
+ * IALS_FLAG_DEAL_QUEUE: wavefronts take rows from a shared atomic queue;
+ * IALS_FLAG_DEAL_STATIC: rows are dealt round-robin in decreasing length order.
+ * Neither: static when the side's mean row length is below 256, else the queue. */
+enum { IALS_FLAG_DEAL_QUEUE = 2u, IALS_FLAG_DEAL_STATIC = 4u };
 
 typedef struct {
     int32_t num_users;          /* U >= 1 */
     int32_t num_items;          /* I >= 1 */
     int32_t dim;                /* d >= 1 */
-    int32_t block;              /* b, 1 <= b <= min(d, 64) */
+    int32_t block;              /* b, 1 <= b <= min(d, 256) (b > 64 runs the workgroup-per-row
+                                   kernels with the block padded to 128 or 256) */
     float alpha0;               /* weight of the all-pairs term, >= 0 */
     float lambda;               /* L2 weight, > 0 */
     int32_t precision;          /* ials_precision */
@@ -80,7 +86,9 @@ typedef struct {
                                    min L_kk^2 < tau * max L_kk^2 (or any pivot <= 0)
                                    is refactored in float64; <= 0 selects 1e-6 */
     uint32_t flags;             /* IALS_FLAG_* bits */
-    uint32_t reserved;
+    uint32_t seg_len;           /* rows longer than this are accumulated in segments of this many
+                                   observations (split-K); a multiple of 64 in [256, 65536];
+                                   0 selects 1024 */
     uint64_t hbm_budget;        /* upper bound on library-owned device bytes; 0 = no bound */
 } ials_config;
 

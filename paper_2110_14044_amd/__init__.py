@@ -17,7 +17,8 @@ class Trainer:
     """Owns device copies of W, H (torch tensors) and one libials context."""
 
     def __init__(self, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
-                 stream=None, device: str = "cuda", hbm_budget: int = 0, graph: bool = False):
+                 stream=None, device: str = "cuda", hbm_budget: int = 0, graph: bool = False, deal: str = "auto",
+                 seg_len: int = 0):
         import numpy as np
         import torch
 
@@ -28,9 +29,11 @@ class Trainer:
         if stream is None:
             stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
         self.stream = stream
+        flags = (binding.IALS_FLAG_GRAPH if graph else 0) | {"auto": 0, "queue": binding.IALS_FLAG_DEAL_QUEUE,
+                                                             "static": binding.IALS_FLAG_DEAL_STATIC}[deal]
         cfg = binding.make_config(problem.num_users, problem.num_items, problem.dim, problem.block,
-                                  problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget,
-                                  binding.IALS_FLAG_GRAPH if graph else 0)
+                                  problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget, flags,
+                                  seg_len)
         u = np.ascontiguousarray(problem.user, np.int32)
         i = np.ascontiguousarray(problem.item, np.int32)
         y = None if problem.y is None else np.ascontiguousarray(problem.y, np.float32)

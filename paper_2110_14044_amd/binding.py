@@ -33,6 +33,8 @@ IALS_MEM_DEVICE = 1
 IALS_PREC_FP32 = 0
 IALS_PREC_BF16 = 1
 IALS_FLAG_GRAPH = 1
+IALS_FLAG_DEAL_QUEUE = 2
+IALS_FLAG_DEAL_STATIC = 4
 
 _STATUS_NAMES = {0: "IALS_OK", -1: "IALS_E_INVALID", -2: "IALS_E_NOMEM", -3: "IALS_E_HIP",
                  -4: "IALS_E_NOT_SPD", -5: "IALS_E_BUSY", -6: "IALS_E_STATE"}
@@ -42,7 +44,7 @@ class ials_config(C.Structure):
     _fields_ = [("num_users", C.c_int32), ("num_items", C.c_int32), ("dim", C.c_int32),
                 ("block", C.c_int32), ("alpha0", C.c_float), ("lambda_", C.c_float),
                 ("precision", C.c_int32), ("chol_fallback_ratio", C.c_float), ("flags", C.c_uint32),
-                ("reserved", C.c_uint32), ("hbm_budget", C.c_uint64)]
+                ("seg_len", C.c_uint32), ("hbm_budget", C.c_uint64)]
 
 
 class ials_coo(C.Structure):
@@ -319,8 +321,8 @@ def ials_version() -> str:
 
 
 def make_config(num_users, num_items, dim, block, alpha0, lam, precision=IALS_PREC_FP32,
-                chol_fallback_ratio=0.0, hbm_budget=0, flags=0) -> ials_config:
-    return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, flags, 0,
+                chol_fallback_ratio=0.0, hbm_budget=0, flags=0, seg_len=0) -> ials_config:
+    return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, flags, seg_len,
                        hbm_budget)
 
 

@@ -136,8 +136,13 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
         g_create_error = "precision must be IALS_PREC_FP32 or IALS_PREC_BF16";
         return IALS_E_INVALID;
     }
-    if ((cfg->flags & ~(uint32_t)IALS_FLAG_GRAPH) != 0) {
-        g_create_error = "unknown flag bits";
+    if ((cfg->flags & ~(uint32_t)(IALS_FLAG_GRAPH | IALS_FLAG_DEAL_QUEUE | IALS_FLAG_DEAL_STATIC)) != 0 ||
+        ((cfg->flags & IALS_FLAG_DEAL_QUEUE) && (cfg->flags & IALS_FLAG_DEAL_STATIC))) {
+        g_create_error = "unknown or conflicting flag bits";
+        return IALS_E_INVALID;
+    }
+    if (cfg->seg_len != 0 && (cfg->seg_len % 64 != 0 || cfg->seg_len < 256 || cfg->seg_len > 65536)) {
+        g_create_error = "seg_len must be 0 or a multiple of 64 in [256, 65536]";
         return IALS_E_INVALID;
     }
     if (S->nnz < 0 || S->nnz > (int64_t)INT32_MAX || (S->nnz > 0 && (!S->user || !S->item)) ||
@@ -167,6 +172,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->lambda = cfg->lambda;
     c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-6f;
     c->precision = cfg->precision;
+    c->seg_len = cfg->seg_len ? (int32_t)cfg->seg_len : ials::kSegLenDefault;
     c->nnz = S->nnz;
     c->stream = (hipStream_t)stream;
     c->W = W;
@@ -347,6 +353,7 @@ ials_status ials_block_sweep(ials_ctx* c, int32_t side, int32_t block) {
 
 ials_status ials_refresh_predictions(ials_ctx* c) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
+    ials::ProfScope ps(c, IALS_K_PREDICT);
     ials::launch_predict(c, c->cur_block, false, c->yhat);
     IALS_HIP_TRY(c, hipGetLastError());
     return IALS_OK;

@@ -211,17 +211,18 @@ __global__ void k_gather(const T* __restrict__ src, const int32_t* __restrict__ 
 }
 
 // Keys for ordering rows by decreasing length (stable: equal lengths keep row order).
-__global__ void k_len_keys(const int64_t* __restrict__ ptr, int32_t nrows, uint64_t* __restrict__ keys,
-                           int32_t* __restrict__ vals, int32_t* __restrict__ nseg) {
+__global__ void k_len_keys(const int64_t* __restrict__ ptr, int32_t nrows, int32_t seg_len,
+                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals, int32_t* __restrict__ nseg) {
     int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
     const int64_t len = ptr[r + 1] - ptr[r];
     keys[r] = 0xFFFFFFFFull - (uint64_t)len;
     vals[r] = r;
-    nseg[r] = (len > kSegLen) ? (int32_t)((len + kSegLen - 1) / kSegLen) : 0;
+    nseg[r] = (len > seg_len) ? (int32_t)((len + seg_len - 1) / seg_len) : 0;
 }
 
-__global__ void k_seg_fill(const int64_t* __restrict__ ptr, int32_t nrows, const int32_t* __restrict__ nseg_scan,
+__global__ void k_seg_fill(const int64_t* __restrict__ ptr, int32_t nrows, int32_t seg_len,
+                           const int32_t* __restrict__ nseg_scan,
                            const int32_t* __restrict__ nseg, int32_t* __restrict__ seg_first,
                            int32_t* __restrict__ seg_row, int64_t* __restrict__ seg_lo, int64_t* __restrict__ seg_hi) {
     int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -236,8 +237,8 @@ __global__ void k_seg_fill(const int64_t* __restrict__ ptr, int32_t nrows, const
     const int64_t lo = ptr[r], hi = ptr[r + 1];
     for (int32_t j = 0; j < cnt; ++j) {
         seg_row[f + j] = r;
-        seg_lo[f + j] = lo + (int64_t)j * kSegLen;
-        seg_hi[f + j] = std::min(hi, lo + (int64_t)(j + 1) * kSegLen);
+        seg_lo[f + j] = lo + (int64_t)j * seg_len;
+        seg_hi[f + j] = std::min(hi, lo + (int64_t)(j + 1) * seg_len);
     }
 }
 
@@ -372,7 +373,7 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         const int32_t nr = s.nrows;
         int32_t* nseg;
         IALS_HIP_TRY(c, tmp.get(&nseg, nr + 1));
-        hipLaunchKernelGGL(k_len_keys, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, keys, vals, nseg);
+        hipLaunchKernelGGL(k_len_keys, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, c->seg_len, keys, vals, nseg);
         IALS_HIP_TRY(c, radix_sort(keys, vals, kalt, valt, nr, 32, hist, sums, st));
         IALS_HIP_TRY(c, hipMemcpyAsync(s.order, vals, sizeof(int32_t) * nr, hipMemcpyDeviceToDevice, st));
         // longest row length (first in the order)
@@ -394,7 +395,7 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
             IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_lo, sizeof(int64_t) * total));
             IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_hi, sizeof(int64_t) * total));
         }
-        hipLaunchKernelGGL(k_seg_fill, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, scan, nseg, s.seg_first,
+        hipLaunchKernelGGL(k_seg_fill, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, c->seg_len, scan, nseg, s.seg_first,
                            s.seg_row, s.seg_lo, s.seg_hi);
         IALS_HIP_TRY(c, hipGetLastError());
         // number of long rows

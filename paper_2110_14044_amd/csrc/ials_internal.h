@@ -15,9 +15,10 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
-// Rows longer than this many observations are split into segments of kSegLen,
-// each accumulated by its own wavefront, then reduced in a fixed order.
-constexpr int kSegLen = 1024;
+// Rows longer than the context's segment length (1024 by default) are split into
+// segments of that many observations, each accumulated by its own wavefront (or
+// workgroup), then reduced in a fixed order.
+constexpr int kSegLenDefault = 1024;
 
 // Device-side counters/flags block (int64), zeroed at create.
 enum Counter : int {
@@ -77,6 +78,7 @@ struct SweepArgs {
     float tau;
     int32_t rows_batch;   // 0: static round-robin rows; 1: rows from the shared queue
     double* fb_scratch;   // float64 Hessians of the wide-block fallback (one B x B per workgroup)
+    int32_t seg_len;      // segment length of long rows
 };
 
 // One fold-in request as the fold-in kernel reads it (from device or pinned host memory).
@@ -108,6 +110,7 @@ struct ials_ctx {
     int32_t U = 0, I = 0, d = 0, b = 0, B = 0;  // B = b padded to a multiple of 16
     float alpha0 = 0.f, lambda = 0.f, tau = 1e-6f;
     int32_t precision = 0;
+    int32_t seg_len = ials::kSegLenDefault;
     int64_t nnz = 0;
     hipStream_t stream = nullptr;
     int device = 0;

@@ -17,7 +17,7 @@
 // c' = yhat - <x_pi', o_pi'>.  This is the same iteration as the delta update of
 // the cached predictions in Alg. 3 (the predictions are equal in exact arithmetic).
 //
-// Rows longer than kSegLen observations are split into segments: k_sweep_seg
+// Rows longer than the segment length are split into segments: k_sweep_seg
 // accumulates each segment's partial Hessian and gradient, the row kernel adds
 // them in segment order (a fixed order, so results are bitwise reproducible) and
 // solves.
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
                 gp[t] += __shfl_xor(gp[t], 32);
             }
         } else {
-            const int ns = (int)((hi - lo + kSegLen - 1) / kSegLen);
+            const int ns = (int)((hi - lo + A.seg_len - 1) / A.seg_len);
             for (int s = sf; s < sf + ns; ++s) {
                 const float* P = A.seg_part + (size_t)s * seg_stride<NT>();
 #pragma unroll
@@ -691,7 +691,8 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     A.counters = c->counters;
     A.tau = c->tau;
     const int64_t avg = s.nrows > 0 ? c->nnz / s.nrows : 0;
-    A.rows_batch = avg < 256 ? 0 : 1;
+    A.rows_batch = (c->flags & IALS_FLAG_DEAL_QUEUE) ? 1 : ((c->flags & IALS_FLAG_DEAL_STATIC) ? 0 : (avg < 256 ? 0 : 1));
+    A.seg_len = c->seg_len;
     const bool trans = blk != c->cur_block;
     if (c->B > 64)
         launch_sweep_big(c, A, s, sd, trans);

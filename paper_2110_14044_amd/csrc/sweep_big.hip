@@ -9,7 +9,7 @@
 // forms the prediction from the cache and the row's own block, and adds
 // a_k x x^T into its own tiles on the matrix cores (float32 16x16x4 per four
 // observations, or bfloat16 16x16x16 per sixteen).  Wave 0 also accumulates the
-// gradient and moves the cache.  Rows longer than kSegLen observations take
+// gradient and moves the cache.  Rows longer than the segment length take
 // per-segment partials instead (k_seg_big), summed in segment order.
 //
 // Factorisation: the tiles go to LDS (packed lower tiles, 256 floats each) and a
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
                 }
             }
         } else {
-            const int ns = (int)((hi - lo + kSegLen - 1) / kSegLen);
+            const int ns = (int)((hi - lo + A.seg_len - 1) / A.seg_len);
             for (int s = sf; s < sf + ns; ++s) {
                 const float* P = A.seg_part + (size_t)s * big_seg_stride<NT>();
 #pragma unroll
