@@ -83,6 +83,10 @@ def lib():
                                _i64p, _i32p, _NullableI32, _Nullable, _Nullable, _f64p, _f64p, _f64p,
                                _f64p]
         L.ora_pass.restype = C.c_int64
+        L.ora_pass_rows.argtypes = [C.c_int32, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                               _i64p, _i32p, _NullableI32, _Nullable, _Nullable, _f64p, _f64p, _f64p,
+                               _f64p]
+        L.ora_pass_rows.restype = C.c_int64
         L.ora_epochs.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                  _i64p, _i32p, _i64p, _i32p, _i32p, _Nullable, _Nullable, _f64p,
                                  _f64p, _f64p, C.c_int32, _Nullable]
@@ -168,6 +172,19 @@ def block_pass(csr: CSR, side: str, p0: int, bw: int, alpha0: float, lam: float,
                               W, H, G, yhat)
     return lib().ora_pass(csr.num_items, d, p0, bw, alpha0, lam, csr.iptr, csr.icol, csr.perm, y, a,
                           H, W, G, yhat)
+
+
+def pass_rows(csr: CSR, side: str, rows, p0: int, bw: int, alpha0: float, lam: float, W: np.ndarray,
+              H: np.ndarray, yhat: np.ndarray, G: np.ndarray, y=None, a=None) -> int:
+    """In place: the block step of the listed rows only (each exactly as in block_pass)."""
+    d = W.shape[1]
+    G = _f64(G)
+    rows = np.ascontiguousarray(rows, np.int32)
+    if side == "user":
+        return lib().ora_pass_rows(rows.size, rows, d, p0, bw, alpha0, lam, csr.uptr, csr.ucol,
+                                   None, y, a, W, H, G, yhat)
+    return lib().ora_pass_rows(rows.size, rows, d, p0, bw, alpha0, lam, csr.iptr, csr.icol, csr.perm, y, a,
+                               H, W, G, yhat)
 
 
 def epochs(csr: CSR, W0, H0, b: int, alpha0: float, lam: float, n_epochs: int, y=None, a=None):

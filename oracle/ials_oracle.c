@@ -279,6 +279,38 @@ int64_t ora_pass(int32_t nrows, int32_t d, int32_t p0, int32_t bw, double alpha0
 }
 
 /*
+ * The same pass restricted to the rows listed in rows[0..nsel): rows are
+ * independent within a pass (sec. 3.2), so each listed row gets exactly the
+ * block step the full pass would give it.  Used to check single rows of
+ * workloads too large for a full float64 pass.
+ */
+int64_t ora_pass_rows(int32_t nsel, const int32_t* rows, int32_t d, int32_t p0, int32_t bw, double alpha0,
+                      double lambda, const int64_t* ptr, const int32_t* col, const int32_t* slot,
+                      const double* y, const double* a, double* Xt, const double* Xo, const double* G,
+                      double* yhat) {
+    int64_t bad = 0;
+#pragma omp parallel reduction(+ : bad)
+    {
+        double* A = (double*)malloc(sizeof(double) * (size_t)bw * bw);
+        double* g = (double*)malloc(sizeof(double) * (size_t)bw);
+        if (!A || !g) {
+            bad += nsel;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int32_t s = 0; s < nsel; ++s) {
+                const int32_t r = rows[s];
+                if (ora_row_step(d, p0, bw, alpha0, lambda, ptr[r], ptr[r + 1], col, slot, y, a,
+                                 Xt + (size_t)r * d, Xo, G, yhat, A, g) != 0)
+                    bad += 1;
+            }
+        }
+        free(A);
+        free(g);
+    }
+    return bad;
+}
+
+/*
  * Full epochs of Algorithm 3.  uptr/ucol: user CSR (yhat order); iptr/icol: item
  * CSR with iperm[k] = user-CSR slot of item slot k.  y, a per user-CSR slot
  * (NULL = ones).  W, H updated in place; yhat (nnz) is scratch and holds the

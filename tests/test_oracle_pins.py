@@ -248,3 +248,26 @@ def test_foldin_limits(oracle_lib):
         prev = cur
     w = oracle.foldin(H, 3, alpha0, lam, ptr, items, 400, y)
     assert np.allclose(w, exact, rtol=1e-8, atol=1e-10)
+
+
+def test_pass_rows_equals_the_full_pass_on_those_rows(oracle_lib):
+    """Rows are independent within a pass (sec. 3.2): the sampled-rows pass gives each listed row
+    exactly the full pass's block step and leaves every other row alone."""
+    import synth
+    p = synth.small_problem(17, 60, 40, 700, 12, 5, labels=True, alpha0=0.2, lam=0.07)
+    csr = oracle.build_csr(p.num_users, p.num_items, p.user, p.item)
+    ys, as_ = oracle.to_slot_order(csr, p.y), oracle.to_slot_order(csr, p.alpha)
+    rng = np.random.default_rng(3)
+    for side, n in (("user", p.num_users), ("item", p.num_items)):
+        W, H = p.W0.astype(np.float64), p.H0.astype(np.float64)
+        yhat = oracle.predict(csr, W, H)
+        G = oracle.gramian(H if side == "user" else W, 5, 5)
+        Wf, Hf, yf = W.copy(), H.copy(), yhat.copy()
+        oracle.block_pass(csr, side, 5, 5, p.alpha0, p.lam, Wf, Hf, yf, G, ys, as_)
+        rows = rng.choice(n, size=n // 3, replace=False)
+        Ws, Hs, ysamp = W.copy(), H.copy(), yhat.copy()
+        oracle.pass_rows(csr, side, rows, 5, 5, p.alpha0, p.lam, Ws, Hs, ysamp, G, ys, as_)
+        full, samp, orig = (Wf, Ws, W) if side == "user" else (Hf, Hs, H)
+        assert np.array_equal(samp[rows], full[rows])
+        rest = np.setdiff1d(np.arange(n), rows)
+        assert np.array_equal(samp[rest], orig[rest])
