@@ -55,6 +55,38 @@ __device__ inline void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
 }
+// Factor storage: the packed lower 16 x 16 tiles of a block, rows padded to 17 floats
+// so that a lane-per-row and a lane-per-column walk both hit distinct LDS banks.
+constexpr int kTP = 17, kTS = 16 * kTP;
+__device__ inline int tid_of(int I, int J) { return I * (I + 1) / 2 + J; }
+__device__ inline void tile_store(float* T, floatx4 c, int lane) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) T[(4 * (lane >> 4) + j) * kTP + (lane & 15)] = c[j];
+}
+__device__ inline floatx4 tile_load(const float* T, int lane) {
+    floatx4 c;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = T[(4 * (lane >> 4) + j) * kTP + (lane & 15)];
+    return c;
+}
+// c += sgn P Q^T and c += sgn P Q for 16 x 16 tiles on the matrix cores
+__device__ inline floatx4 mm_pqt(floatx4 c, const float* P, const float* Q, float sgn, int lane) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int o = (lane & 15) * kTP + 4 * s4 + (lane >> 4);
+        c = mfma4(sgn * P[o], Q[o], c);
+    }
+    return c;
+}
+__device__ inline floatx4 mm_pq(floatx4 c, const float* P, const float* Q, float sgn, int lane) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + (lane >> 4);
+        c = mfma4(sgn * P[(lane & 15) * kTP + k], Q[k * kTP + (lane & 15)], c);
+    }
+    return c;
+}
+
 __device__ inline int item_at(const int32_t* items, int k, int I) {
     const int it = items[k];
     return (unsigned)it < (unsigned)I ? it : 0;  // ids are checked in phase 0; clamp keeps loads in bounds
@@ -163,7 +195,7 @@ __device__ void foldin_f64(const FoldArgs& A, const FoldReq& R, int n, const int
 
 template <int NT, bool GFAC>
 __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
-    constexpr int B = 16 * NT, PB = B + 1, NTL = NT * (NT + 1) / 2;
+    constexpr int B = 16 * NT, NTL = NT * (NT + 1) / 2;
     extern __shared__ __align__(16) float sm[];
     const int tid = threadIdx.x, lane = tid & 63, q16 = lane & 15, g4 = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -173,7 +205,8 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
     float* gv = part + 8 * B;      // [4][B] per-wave gradient
     float* tv = gv + 4 * B;        // [4][B] per-wave X g
     float* dv = tv + 4 * B;        // [4][B] per-wave step delta
-    int* flag = reinterpret_cast<int*>(dv + 4 * B);            // [4]: float64 redo, bad id, not SPD
+    float* tmp_all = dv + 4 * B;   // [4][kTS] per-wave scratch tile
+    int* flag = reinterpret_cast<int*>(tmp_all + 4 * kTS);     // [4]: float64 redo, bad id, not SPD
     int32_t* items_l = reinterpret_cast<int32_t*>(flag + 4);  // [nl] ids of a request of <= nl items
     float* res_l = reinterpret_cast<float*>(items_l + nl);    // [nl] its residuals yhat - y
     float* tail = res_l + nl;      // inverse factors (LDS mode) or the float64 work area
@@ -240,66 +273,102 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                         for (int J = 0; J <= I; ++J)
                             acc[I * (I + 1) / 2 + J] = mfma4(x[s16][I], x[s16][J], acc[I * (I + 1) / 2 + J]);
             }
-            float* L = fac + (size_t)blk * B * PB;
+            float* Lt = fac + (size_t)blk * NTL * kTS;
             // lower tiles plus alpha0 G[pi,pi] + lambda I (identity on the padding)
 #pragma unroll
             for (int I = 0; I < NT; ++I)
 #pragma unroll
-                for (int J = 0; J <= I; ++J)
+                for (int J = 0; J <= I; ++J) {
+                    floatx4 c = acc[I * (I + 1) / 2 + J];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int row = 16 * I + 4 * g4 + j, col = 16 * J + q16;
-                        float v0;
                         if (row < bw && col < bw)
-                            v0 = A.alpha0 * A.G[(size_t)(p0 + row) * d + p0 + col] + (row == col ? A.lambda : 0.f);
+                            c[j] += A.alpha0 * A.G[(size_t)(p0 + row) * d + p0 + col] + (row == col ? A.lambda : 0.f);
                         else
-                            v0 = (row == col) ? 1.f : 0.f;
-                        L[row * PB + col] = acc[I * (I + 1) / 2 + J][j] + v0;
+                            c[j] += (row == col) ? 1.f : 0.f;
                     }
+                    tile_store(Lt + tid_of(I, J) * kTS, c, lane);
+                }
             wave_fence();
-            // Right-looking Cholesky, lane i holding row i: step k scales column k by
-            // 1/sqrt(A_kk) and subtracts L_ik L_jk from the later columns j of row i.
-            // Entries right of the diagonal are never read (they hold leftovers).
-            const int i = lane < B ? lane : 0;
-            float a[B];
-#pragma unroll
-            for (int k = 0; k < B; ++k) a[k] = L[i * PB + k];
+            // Blocked right-looking Cholesky over the tiles (rolled loops, so the code stays in the
+            // instruction cache): the diagonal tile is factored lane-per-row and inverted
+            // (Y = L_KK^-1 replaces it), the panel becomes L_IK = A_IK Y^T and the trailing tiles
+            // lose L_IK L_JK^T, both on the matrix cores.
+            float* tmp = tmp_all + wave * kTS;
+            const int i16 = lane & 15;
             float pmin = 3.0e38f, pmax = 0.f;
+#pragma unroll 1
+            for (int K = 0; K < NT; ++K) {
+                float* TK = Lt + tid_of(K, K) * kTS;
+                float a[16];
 #pragma unroll
-            for (int k = 0; k < B; ++k) {
-                const float piv = readlane(a[k], k);
-                if (k < bw) {
-                    pmin = fminf(pmin, piv);
-                    pmax = fmaxf(pmax, piv);
+                for (int k = 0; k < 16; ++k) a[k] = TK[i16 * kTP + k];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const float piv = readlane(a[k], k);
+                    if (16 * K + k < bw) {
+                        pmin = fminf(pmin, piv);
+                        pmax = fmaxf(pmax, piv);
+                    }
+                    const float rs = piv > 0.f ? __builtin_amdgcn_rsqf(piv) : 0.f;
+                    const float l = a[k] * rs;
+                    a[k] = l;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) a[j] = fmaf(-l, readlane(l, j), a[j]);
                 }
-                const float rs = piv > 0.f ? __builtin_amdgcn_rsqf(piv) : 0.f;
-                const float l = a[k] * rs;
-                a[k] = l;
+                float y[16];
 #pragma unroll
-                for (int j = k + 1; j < B; ++j) a[j] = fmaf(-l, readlane(l, j), a[j]);
-            }
-            const bool bad = !(pmin > 0.f) || pmin < A.tau * pmax;
-            if (bad && lane == 0) flag[0] = 1;
-            // X = L^-1 by columns, lane j holding column j: X_jj = 1/L_jj and, for i > j,
-            // X_ij = -(sum_{j <= k < i} L_ik X_kj) / L_ii (row i of L is lane i's registers).
-            float x[B];
+                for (int ii = 0; ii < 16; ++ii) {
+                    float s0 = 0.f;
 #pragma unroll
-            for (int ii = 0; ii < B; ++ii) {
-                float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-                for (int k = 0; k + 1 < ii; k += 2) {
-                    s0 = fmaf(readlane(a[k], ii), x[k], s0);
-                    s1 = fmaf(readlane(a[k + 1], ii), x[k + 1], s1);
+                    for (int k = 0; k < ii; ++k) s0 = fmaf(readlane(a[k], ii), y[k], s0);
+                    const float di = 1.f / readlane(a[ii], ii);
+                    y[ii] = (ii < i16) ? 0.f : (ii == i16 ? di : -s0 * di);
                 }
-                if (ii & 1) s0 = fmaf(readlane(a[ii - 1], ii), x[ii - 1], s0);
-                const float di = 1.f / readlane(a[ii], ii);
-                x[ii] = (ii < lane) ? 0.f : (ii == lane ? di : -(s0 + s1) * di);
-            }
-            wave_fence();
-            if (lane < B) {
+                wave_fence();
+                if (lane < 16) {
 #pragma unroll
-                for (int ii = 0; ii < B; ++ii) L[ii * PB + lane] = x[ii];
+                    for (int ii = 0; ii < 16; ++ii) TK[ii * kTP + lane] = y[ii];
+                }
+                wave_fence();
+#pragma unroll 1
+                for (int I = K + 1; I < NT; ++I) {
+                    float* P = Lt + tid_of(I, K) * kTS;
+                    const floatx4 c = mm_pqt(floatx4{0.f, 0.f, 0.f, 0.f}, P, TK, 1.f, lane);
+                    wave_fence();
+                    tile_store(P, c, lane);
+                }
+                wave_fence();
+#pragma unroll 1
+                for (int I = K + 1; I < NT; ++I)
+#pragma unroll 1
+                    for (int J = K + 1; J <= I; ++J) {
+                        float* T = Lt + tid_of(I, J) * kTS;
+                        floatx4 c = tile_load(T, lane);
+                        c = mm_pqt(c, Lt + tid_of(I, K) * kTS, Lt + tid_of(J, K) * kTS, -1.f, lane);
+                        tile_store(T, c, lane);
+                    }
+                wave_fence();
             }
+            if ((!(pmin > 0.f) || pmin < A.tau * pmax) && lane == 0) flag[0] = 1;
+            // X = L^-1 in place, row by row, each row's tiles in ascending column order:
+            // X_II = Y_II (already there) and X_IJ = -Y_II sum_{J <= K < I} L_IK X_KJ.
+#pragma unroll 1
+            for (int I = 1; I < NT; ++I)
+#pragma unroll 1
+                for (int J = 0; J < I; ++J) {
+                    floatx4 sacc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+                    for (int K = J; K < I; ++K)
+                        sacc = mm_pq(sacc, Lt + tid_of(I, K) * kTS, Lt + tid_of(K, J) * kTS, 1.f, lane);
+                    tile_store(tmp, sacc, lane);
+                    wave_fence();
+                    const floatx4 xv = mm_pq(floatx4{0.f, 0.f, 0.f, 0.f}, Lt + tid_of(I, I) * kTS, tmp, -1.f, lane);
+                    wave_fence();
+                    tile_store(Lt + tid_of(I, J) * kTS, xv, lane);
+                    wave_fence();
+                }
         }
         __syncthreads();
 
@@ -318,16 +387,16 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
             for (int pass = 0; pass < A.passes; ++pass) {
                 for (int blk = 0; blk < A.nb; ++blk, ++step) {
                     const int p0 = blk * A.b, bw = min(A.b, d - p0);
-                    const float* X = fac + (size_t)blk * B * PB;
+                    const float* Xt = fac + (size_t)blk * NTL * kTS;
                     const int col = p0 + (lane < bw ? lane : 0);
                     // dense part: alpha0 sum_f w_f G[f][p0 + lane] over this wave's rows f
                     float sd0 = 0.f, sd1 = 0.f;
-                    for (int f = f_lo; f < f_hi; f += 16) {
-                        float gg[16];
+                    for (int f = f_lo; f < f_hi; f += 64) {
+                        float gg[64];
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) gg[q] = A.G[(size_t)min(f + q, f_hi - 1) * d + col];
+                        for (int q = 0; q < 64; ++q) gg[q] = A.G[(size_t)min(f + q, f_hi - 1) * d + col];
 #pragma unroll
-                        for (int q = 0; q < 16; q += 2) {
+                        for (int q = 0; q < 64; q += 2) {
                             const float w0 = (f + q < f_hi) ? wme[f + q] : 0.f;
                             const float w1 = (f + q + 1 < f_hi) ? wme[f + q + 1] : 0.f;
                             sd0 = fmaf(w0, gg[q], sd0);
@@ -368,16 +437,16 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                             }
                         }
                         const int cnt = min(64, nv - m0);
-                        for (int t = 0; t < cnt; t += 8) {
-                            float h[8], rr[8];
+                        for (int t = 0; t < cnt; t += 16) {
+                            float h[16], rr[16];
 #pragma unroll
-                            for (int s8 = 0; s8 < 8; ++s8) {
+                            for (int s8 = 0; s8 < 16; ++s8) {
                                 const int it = __builtin_amdgcn_readlane(itl, t + s8);
                                 rr[s8] = readlane(rl, t + s8);
                                 h[s8] = A.H[(size_t)it * d + col];
                             }
 #pragma unroll
-                            for (int s8 = 0; s8 < 8; s8 += 2) {
+                            for (int s8 = 0; s8 < 16; s8 += 2) {
                                 so0 = fmaf(rr[s8], h[s8], so0);
                                 so1 = fmaf(rr[s8 + 1], h[s8 + 1], so1);
                             }
@@ -392,22 +461,33 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                                                     A.lambda * wme[p0 + lane]
                                               : 0.f;
                     wave_fence();
+                    // t = X g (lane i: row i of X, tiles (I, K) for K <= I), then delta = X^T t
+                    // (lane p: column p of X, tiles (I, P) for I >= P); X is lower triangular
                     const int i = lane < B ? lane : 0;
-                    float t0 = 0.f, t1 = 0.f;
+                    const int Ii = i >> 4, ri = i & 15;
+                    float t4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int k = 0; k < B; k += 2) {
-                        t0 = fmaf(X[i * PB + k], gme[k], t0);
-                        t1 = fmaf(X[i * PB + k + 1], gme[k + 1], t1);
+                    for (int K = 0; K < NT; ++K) {
+                        const float* row = Xt + tid_of(Ii >= K ? Ii : K, K) * kTS + ri * kTP;
+#pragma unroll
+                        for (int kk = 0; kk < 16; ++kk) {
+                            const float v = row[kk];
+                            t4[kk & 3] = fmaf(K <= Ii ? v : 0.f, gme[16 * K + kk], t4[kk & 3]);
+                        }
                     }
-                    if (lane < B) tme[lane] = t0 + t1;
+                    if (lane < B) tme[lane] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
                     wave_fence();
-                    float e0 = 0.f, e1 = 0.f;
+                    float e4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int k = 0; k < B; k += 2) {
-                        e0 = fmaf(X[k * PB + i], tme[k], e0);
-                        e1 = fmaf(X[(k + 1) * PB + i], tme[k + 1], e1);
+                    for (int I = 0; I < NT; ++I) {
+                        const float* colp = Xt + tid_of(I >= Ii ? I : Ii, Ii) * kTS + ri;
+#pragma unroll
+                        for (int rr = 0; rr < 16; ++rr) {
+                            const float v = colp[rr * kTP];
+                            e4[rr & 3] = fmaf(I >= Ii ? v : 0.f, tme[16 * I + rr], e4[rr & 3]);
+                        }
                     }
-                    const float del = e0 + e1;
+                    const float del = (e4[0] + e4[1]) + (e4[2] + e4[3]);
                     if (lane < B) dme[lane] = lane < bw ? del : 0.f;
                     if (lane < bw) wme[p0 + lane] -= del;
                     wave_fence();
@@ -435,9 +515,14 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
 
 constexpr size_t kFoldLdsMax = 150 * 1024;
 
-size_t lds_head_bytes(int32_t d, int32_t B, int32_t nl) { return (size_t)(4 * ((d + 3) & ~3) + 20 * B + 4 + 2 * nl) * 4; }
+size_t lds_head_bytes(int32_t d, int32_t B, int32_t nl) {
+    return (size_t)(4 * ((d + 3) & ~3) + 20 * B + 4 * kTS + 4 + 2 * nl) * 4;
+}
 size_t lds_f64_bytes(int32_t d, int32_t B) { return (size_t)(B * B + ((d + 3) & ~3) + 2 * B) * 8; }
-size_t lds_fac_bytes(int32_t nb, int32_t B) { return (size_t)nb * B * (B + 1) * 4; }
+size_t lds_fac_bytes(int32_t nb, int32_t B) {
+    const int nt = B / 16;
+    return (size_t)nb * (nt * (nt + 1) / 2) * kTS * 4;
+}
 
 template <int NT, bool GFAC>
 hipError_t launch_nt(hipStream_t st, const FoldShape& f, const FoldArgs& a) {
@@ -480,7 +565,7 @@ FoldShape fold_shape(int32_t I, int32_t d, int32_t b) {
 
 size_t fold_ws_floats(const FoldShape& f, int64_t n) {
     const size_t base = ws_fac_off(n);
-    return base + (f.gfac ? ((size_t)f.nb * f.B * (f.B + 1) + 63) / 64 * 64 : 0);
+    return base + (f.gfac ? (lds_fac_bytes(f.nb, f.B) / 4 + 63) / 64 * 64 : 0);
 }
 
 hipError_t launch_foldin(hipStream_t st, const FoldShape& f, const float* H, const float* G, float alpha0,
