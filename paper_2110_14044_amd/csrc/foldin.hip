@@ -10,9 +10,9 @@
 //   w[pi] -= Hess^-1 grad,   yhat_k -= <delta, h_{i_k}[pi]>
 // with G = H^T H.  H is fixed, so every block's Hessian is the same in every
 // sweep: it is accumulated on the matrix cores and Cholesky-factored once per
-// request, and the factor is inverted (X = L^-1, lower triangular), so that a
-// block step is a gradient, two small matrix-vector products
-// (delta = X^T (X grad)) and the updates, with no sequential solve.
+// request and turned into the block's inverse Hessian (X = L^-1, then X^T X), so
+// that a block step is a gradient, one small matrix-vector product and the
+// updates, with no sequential solve.
 //
 // One workgroup (4 wavefronts) per request.  Phase 1: the waves factor and
 // invert blocks in parallel (wave v takes blocks v, v+4, ...), keeping X in
@@ -75,6 +75,15 @@ __device__ inline floatx4 mm_pqt(floatx4 c, const float* P, const float* Q, floa
     for (int s4 = 0; s4 < 4; ++s4) {
         const int o = (lane & 15) * kTP + 4 * s4 + (lane >> 4);
         c = mfma4(sgn * P[o], Q[o], c);
+    }
+    return c;
+}
+// c += P^T Q
+__device__ inline floatx4 mm_ptq(floatx4 c, const float* P, const float* Q, int lane) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int o = (4 * s4 + (lane >> 4)) * kTP + (lane & 15);
+        c = mfma4(P[o], Q[o], c);
     }
     return c;
 }
@@ -266,12 +275,14 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                     }
                 }
 #pragma unroll
-                for (int s16 = 0; s16 < 16; ++s16)
+                for (int s16 = 0; s16 < 16; ++s16) {
+                    if (k0 + 4 * s16 >= n) break;  // uniform: the rest of the round is empty
 #pragma unroll
                     for (int I = 0; I < NT; ++I)
 #pragma unroll
                         for (int J = 0; J <= I; ++J)
                             acc[I * (I + 1) / 2 + J] = mfma4(x[s16][I], x[s16][J], acc[I * (I + 1) / 2 + J]);
+                }
             }
             float* Lt = fac + (size_t)blk * NTL * kTS;
             // lower tiles plus alpha0 G[pi,pi] + lambda I (identity on the padding)
@@ -369,6 +380,20 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                     tile_store(Lt + tid_of(I, J) * kTS, xv, lane);
                     wave_fence();
                 }
+            // Hess^-1 = X^T X, lower tiles in place: M_PQ = sum_{I >= P} X_IP^T X_IQ.  Going
+            // through P, then Q, ascending, no X tile is overwritten before its last use.
+#pragma unroll 1
+            for (int P = 0; P < NT; ++P)
+#pragma unroll 1
+                for (int Q = 0; Q <= P; ++Q) {
+                    floatx4 macc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+                    for (int I = P; I < NT; ++I)
+                        macc = mm_ptq(macc, Lt + tid_of(I, P) * kTS, Lt + tid_of(I, Q) * kTS, lane);
+                    wave_fence();
+                    tile_store(Lt + tid_of(P, Q) * kTS, macc, lane);
+                    wave_fence();
+                }
         }
         __syncthreads();
 
@@ -403,53 +428,49 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                             sd1 = fmaf(w1, gg[q + 1], sd1);
                         }
                     }
-                    // observations: previous step applied to the residuals, then res_k h_k[p0 + lane]
+                    // observations: previous step applied to the residuals, then res_k h_k[p0 + lane].
+                    // Every load of a round (the previous block's row for the residual update, the
+                    // current block's values for the gradient) is issued before any is used.
                     float so0 = 0.f, so1 = 0.f;
                     for (int m0 = 0; m0 < nv; m0 += 64) {
                         const int k = wave + 4 * (m0 + lane);
-                        int itl = 0;
-                        float rl = 0.f;
-                        if (k < n) {
-                            itl = item_at(items, k, A.I);
-                            rl = res[k];
-                            if (step > 0) {
-                                const float* hr = A.H + (size_t)itl * d + pp0;
-                                float e0 = 0.f, e1 = 0.f;
-                                if (vec) {
-                                    for (int j = 0; j < pbw; j += 8) {
-                                        const float4 h0 = *reinterpret_cast<const float4*>(hr + j);
-                                        const float4 h1 = (j + 4 < pbw) ? *reinterpret_cast<const float4*>(hr + j + 4)
-                                                                        : float4{0.f, 0.f, 0.f, 0.f};
-                                        e0 = fmaf(dme[j], h0.x, e0);
-                                        e0 = fmaf(dme[j + 1], h0.y, e0);
-                                        e0 = fmaf(dme[j + 2], h0.z, e0);
-                                        e0 = fmaf(dme[j + 3], h0.w, e0);
-                                        e1 = fmaf(dme[j + 4], h1.x, e1);
-                                        e1 = fmaf(dme[j + 5], h1.y, e1);
-                                        e1 = fmaf(dme[j + 6], h1.z, e1);
-                                        e1 = fmaf(dme[j + 7], h1.w, e1);
-                                    }
-                                } else {
-                                    for (int j = 0; j < pbw; ++j) e0 = fmaf(dme[j], hr[j], e0);
-                                }
-                                rl -= e0 + e1;
-                                res[k] = rl;
-                            }
-                        }
+                        const bool kv = k < n;
+                        const int itl = kv ? item_at(items, k, A.I) : 0;
+                        float rl = kv ? res[k] : 0.f;
                         const int cnt = min(64, nv - m0);
-                        for (int t = 0; t < cnt; t += 16) {
-                            float h[16], rr[16];
+                        float hg[64];
 #pragma unroll
-                            for (int s8 = 0; s8 < 16; ++s8) {
-                                const int it = __builtin_amdgcn_readlane(itl, t + s8);
-                                rr[s8] = readlane(rl, t + s8);
-                                h[s8] = A.H[(size_t)it * d + col];
-                            }
+                        for (int s8 = 0; s8 < 64; ++s8) {
+                            const int it = __builtin_amdgcn_readlane(itl, s8);
+                            hg[s8] = (s8 < cnt) ? A.H[(size_t)it * d + col] : 0.f;
+                        }
+                        if (step > 0) {
+                            const float* hr = A.H + (size_t)itl * d + pp0;
+                            float e0 = 0.f, e1 = 0.f;
+                            if (vec) {
+                                float4 hv[16];
 #pragma unroll
-                            for (int s8 = 0; s8 < 16; s8 += 2) {
-                                so0 = fmaf(rr[s8], h[s8], so0);
-                                so1 = fmaf(rr[s8 + 1], h[s8 + 1], so1);
+                                for (int j4 = 0; j4 < 16; ++j4)
+                                    hv[j4] = (4 * j4 < pbw) ? *reinterpret_cast<const float4*>(hr + 4 * j4)
+                                                            : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                                for (int j4 = 0; j4 < 16; ++j4) {
+                                    const float4 dd = *reinterpret_cast<const float4*>(dme + 4 * j4);
+                                    e0 = fmaf(dd.x, hv[j4].x, e0);
+                                    e1 = fmaf(dd.y, hv[j4].y, e1);
+                                    e0 = fmaf(dd.z, hv[j4].z, e0);
+                                    e1 = fmaf(dd.w, hv[j4].w, e1);
+                                }
+                            } else {
+                                for (int j = 0; j < pbw; ++j) e0 = fmaf(dme[j], hr[j], e0);
                             }
+                            rl -= e0 + e1;
+                            if (kv) res[k] = rl;
+                        }
+#pragma unroll
+                        for (int s8 = 0; s8 < 64; s8 += 2) {
+                            so0 = fmaf(readlane(rl, s8), hg[s8], so0);
+                            so1 = fmaf(readlane(rl, s8 + 1), hg[s8 + 1], so1);
                         }
                     }
                     float* pb = part + (step & 1) * 4 * B;
@@ -461,33 +482,23 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                                                     A.lambda * wme[p0 + lane]
                                               : 0.f;
                     wave_fence();
-                    // t = X g (lane i: row i of X, tiles (I, K) for K <= I), then delta = X^T t
-                    // (lane p: column p of X, tiles (I, P) for I >= P); X is lower triangular
+                    (void)tme;
+                    // delta = Hess^-1 g with the inverse's lower tiles: lane p walks row p of the tiles
+                    // left of (and on) the diagonal and column p of the tiles below it
                     const int i = lane < B ? lane : 0;
                     const int Ii = i >> 4, ri = i & 15;
                     float t4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int K = 0; K < NT; ++K) {
-                        const float* row = Xt + tid_of(Ii >= K ? Ii : K, K) * kTS + ri * kTP;
+                        const bool below = K > Ii;
+                        const float* tp = Xt + (below ? tid_of(K, Ii) : tid_of(Ii, K)) * kTS;
 #pragma unroll
                         for (int kk = 0; kk < 16; ++kk) {
-                            const float v = row[kk];
-                            t4[kk & 3] = fmaf(K <= Ii ? v : 0.f, gme[16 * K + kk], t4[kk & 3]);
+                            const float v = below ? tp[kk * kTP + ri] : tp[ri * kTP + kk];
+                            t4[kk & 3] = fmaf(v, gme[16 * K + kk], t4[kk & 3]);
                         }
                     }
-                    if (lane < B) tme[lane] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
-                    wave_fence();
-                    float e4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int I = 0; I < NT; ++I) {
-                        const float* colp = Xt + tid_of(I >= Ii ? I : Ii, Ii) * kTS + ri;
-#pragma unroll
-                        for (int rr = 0; rr < 16; ++rr) {
-                            const float v = colp[rr * kTP];
-                            e4[rr & 3] = fmaf(I >= Ii ? v : 0.f, tme[16 * I + rr], e4[rr & 3]);
-                        }
-                    }
-                    const float del = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+                    const float del = (t4[0] + t4[1]) + (t4[2] + t4[3]);
                     if (lane < B) dme[lane] = lane < bw ? del : 0.f;
                     if (lane < bw) wme[p0 + lane] -= del;
                     wave_fence();
