@@ -57,16 +57,19 @@ def rows_work(lengths, b, trans_fraction):
     return flops, bytes_
 
 
-def measured_traffic(kernel_family):
+def measured_traffic(kernel_family, workload, block, precision):
     """HBM bytes per launch from the committed counter summary, or None if the sweep kernels
-    changed since the counters were taken (or the summary is for another kernel)."""
+    changed since the counters were taken (or the summary is for another kernel or workload)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_k_sweep_rows_ml20m_like.txt")
     if not os.path.exists(path):
         return None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
     src = os.path.join(ROOT, "paper_2110_14044_amd", "csrc", "sweep.hip")
-    if kv.get("kernel") != kernel_family or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get(
+    if (kv.get("kernel"), kv.get("workload"), kv.get("block"), kv.get("precision")) != (
+            kernel_family, workload, str(block), precision):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get(
             "sweep_hip_sha256"):
         return None
     return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
@@ -307,7 +310,7 @@ def main():
     roofline = {
         "kernel": kname + ": gather + MFMA Hessian + blocked Cholesky + update",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(dom),
+        "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(dom, wl.name, p.block, args.precision),
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
         "avg_launch_ms": kern[dom]["avg_ms"],
         "algorithmic_GBps": round(bytes_ / avg_s / 1e9, 1),
