@@ -298,12 +298,176 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
     dtiles[e] = Dmat[colmap<NT, FULL>(16 * ti + 4 * (lq >> 4) + j) * B + colmap<NT, FULL>(16 * tj + (lq & 15))];
 }
 
+// Zero rows read by the back substitution in place of panel rows a lane does not use.
+constexpr int kZeroFloats = 16 * kPS;
+
+// p += t * (lane J of this lane's 16-lane row of D): v_fmac_f32 with a DPP row_newbcast
+// source operand.  The first update of a step begins with two wait states, as a DPP read
+// of a VGPR that a VALU instruction has just written requires; the updates of one step are
+// volatile so they keep their order and D is not rewritten between them.
+template <int J, bool FIRST>
+__device__ inline void fmac_rowbcast(float& p, float D, float t) {
+    if constexpr (FIRST)
+        asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(p)
+                     : "v"(D), "v"(t), "i"(J));
+    else
+        asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(p)
+                     : "v"(D), "v"(t), "i"(J));
+}
+// Columns JJ..15 of one elimination step: p[jj] += D(row lane jj) * t.
+template <int JJ, bool FIRST>
+__device__ inline void eliminate_cols(float* p, float D, float t) {
+    if constexpr (JJ < 16) {
+        fmac_rowbcast<JJ, FIRST>(p[JJ], D, t);
+        eliminate_cols<JJ + 1, false>(p, D, t);
+    }
+}
+// Steps KK..15 of panel K (see ldl_solve).  src: ds_bpermute address of the lane of row
+// group K in this lane's row position; lk = this lane's row - 16K (-1 - 16K past the block).
+template <int K, int KK>
+__device__ inline void panel_steps(float* p, float& g, float& mypiv, float lk, int src) {
+    if constexpr (KK < 16) {
+        constexpr int k = 16 * K + KK;
+        const float piv = readlane(p[KK], k);
+        // lane k keeps the pivot (two wait states: piv was just written by a VALU readlane)
+        asm volatile("s_nop 1\n\tv_writelane_b32 %0, %1, %2" : "+v"(mypiv) : "s"(piv), "i"(k));
+        const float nr = __builtin_amdgcn_rcpf(-piv);
+        const float act = __builtin_amdgcn_fmed3f(lk - (float)KK, 0.f, 1.f);  // 1 in the lanes below row k
+        const float tn = p[KK] * nr * act;              // -t_i
+        if constexpr (KK < 15) {
+            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p[KK])));
+            eliminate_cols<KK + 1, true>(p, D, tn);
+        }
+        g = fmaf(tn, readlane(g, k), g);
+        p[KK] = tn;
+        panel_steps<K, KK + 1>(p, g, mypiv, lk, src);
+    }
+}
+
+// Solve Hess x = g for one row with the Hessian in the accumulator tiles (lower tiles, p
+// order) and lane p < B holding g_p: a blocked right-looking LDL^T factorisation with the
+// forward substitution folded in, then the back substitution.  Returns false (in every lane)
+// when a pivot is not positive or below tau * (largest pivot) over the real coordinates.
+//
+// Panel K (16 columns) is moved to the lane-per-row layout through LDS (lane i holds
+// A_{i, 16K..16K+15} in p[]).  Step k = 16K + kk: piv = A_kk; lanes i > k take
+// t_i = A_ik / piv (0 in the other lanes), g_i -= t_i g_k and A_ij -= t_i A_jk for the
+// panel's later columns j, where column k of the diagonal tile (held by the lanes of row
+// group K) is first copied to every row group and then read with a row broadcast.  Lane i
+// keeps -t_i in place of A_ik, so a finished panel holds -L (unit lower factor, zeros on and
+// above the diagonal), which the back substitution reads column-wise.  The trailing tiles
+// take A_IJ -= L_IK diag(piv) L_JK^T on the matrix cores.
+template <int NT, int K>
+__device__ inline void ldl_panels(floatx4* acc, float& g, float* pan, int ln, float li, float& mypiv) {
+    if constexpr (K < NT) {
+        constexpr int B = 16 * NT;
+        const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+        float* PK = pan + panel_row0<NT>(K) * kPS;  // row r >= 16K at PK + (r - 16K) * kPS
+#pragma unroll
+        for (int I = K; I < NT; ++I) {
+            const int id = I * (I + 1) / 2 + K;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) PK[(16 * (I - K) + 4 * g4 + j) * kPS + q16] = acc[id][j];
+        }
+        wave_lds_fence();
+        const bool mine = (ln >= 16 * K) && (ln < B);
+        const int prow = mine ? ln - 16 * K : 0;
+        float p[16];
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const float4 v = *reinterpret_cast<const float4*>(PK + prow * kPS + 4 * c4);
+            p[4 * c4 + 0] = v.x;
+            p[4 * c4 + 1] = v.y;
+            p[4 * c4 + 2] = v.z;
+            p[4 * c4 + 3] = v.w;
+        }
+        wave_lds_fence();
+        panel_steps<K, 0>(p, g, mypiv, li - 16.f * K, (16 * K + (ln & 15)) * 4);
+        if (mine) {
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                *reinterpret_cast<float4*>(PK + prow * kPS + 4 * c4) =
+                    make_float4(p[4 * c4], p[4 * c4 + 1], p[4 * c4 + 2], p[4 * c4 + 3]);
+        }
+        wave_lds_fence();
+        // trailing tiles: A_IJ -= L_IK diag(piv) L_JK^T for K < J <= I (the panel holds -L)
+        if constexpr (K + 1 < NT) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const float npm = -__int_as_float(
+                    __builtin_amdgcn_ds_bpermute((16 * K + 4 * s4 + g4) * 4, __float_as_int(mypiv)));
+                float op[NT];
+#pragma unroll
+                for (int I = K + 1; I < NT; ++I) op[I] = PK[(16 * (I - K) + q16) * kPS + 4 * s4 + g4];
+#pragma unroll
+                for (int I = K + 1; I < NT; ++I) {
+                    const float a = op[I] * npm;
+#pragma unroll
+                    for (int J = K + 1; J <= I; ++J) {
+                        const int id = I * (I + 1) / 2 + J;
+                        acc[id] = mfma4(a, op[J], acc[id]);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ldl_panels<NT, K + 1>(acc, g, pan, ln, li, mypiv);
+    }
+}
+
+template <int NT>
+__device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, const float* zero_lds, int ln, float tau,
+                                 int my_col, int bw, float& x) {
+    constexpr int B = 16 * NT;
+    const float li = (ln < B) ? (float)ln : -1.f;  // lanes past the block never take a step
+    float mypiv = 1.f;                             // lane k: the pivot of step k
+    ldl_panels<NT, 0>(acc, g, pan, ln, li, mypiv);
+    // pivot check over the real (unpadded) coordinates
+    const bool real = (ln < B) && (my_col < bw);
+    float pmin = real ? mypiv : 3.0e38f;
+    float pmax = real ? mypiv : 0.f;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        pmin = fminf(pmin, __shfl_xor(pmin, m));
+        pmax = fmaxf(pmax, __shfl_xor(pmax, m));
+    }
+    // identical in every lane after the reductions; made explicitly uniform so the
+    // row loop stays a uniform loop (its queue step needs the whole wave)
+    const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < tau * pmax)) ? 1 : 0);
+    if (bad) return false;
+    // w = D^-1 L^-1 g, then L^T x = w from the last column: x_k = w_k once every later column
+    // has been applied, then w_i += (-L_ki) x_k for i < k (lane i reads row k of the panel
+    // that holds column i; lanes whose panel comes after row k read zeros).
+    float wv = g * __builtin_amdgcn_rcpf(mypiv);
+    const int pk = ln >> 4;
+    const int pbase = panel_row0<NT>(pk < NT ? pk : 0) - 16 * pk;
+#pragma unroll
+    for (int K = NT - 1; K >= 0; --K) {
+        const bool ok = (pk <= K) && (ln < B);
+        const float* rowp = ok ? pan + (pbase + 16 * K) * kPS + (ln & 15) : zero_lds + (ln & 15);
+        float lt[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) lt[jj] = rowp[jj * kPS];
+#pragma unroll
+        for (int jj = 15; jj >= 0; --jj) wv = fmaf(lt[jj], readlane(wv, 16 * K + jj), wv);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_lds_fence();
+    x = wv;
+    return true;
+}
+
 template <int NT, bool FULL, bool TRANS, bool STATIC, bool BF>
 __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     float* pan = lds_all + wave * rows_lds_floats_per_wave<NT>();
+    float* zero_lds = lds_all + rows_lds_floats<NT>();
+    for (int e = threadIdx.x; e < kZeroFloats; e += 256) zero_lds[e] = 0.f;
+    __syncthreads();
     const int my_col = colmap<NT, FULL>(lane < B ? lane : 0);
 
     // STATIC: rows are dealt round-robin in the length order (sides whose rows are all
@@ -349,131 +513,21 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
             if (g4 == t) g = gp[t];
         if (lane < B) g += A.R0[(size_t)r * B + my_col];
 
-        // The lane id is laundered once per row so that lane-vs-k masks below are
-        // formed inside the row, not hoisted out of the row loop into scalar registers.
+        // The lane id is laundered once per row so that the lane-dependent values below
+        // are formed inside the row, not hoisted out of the row loop into registers.
         int ln = lane;
         asm volatile("" : "+v"(ln));
-
-        // Blocked right-looking Cholesky on the accumulator tiles, 16 columns per panel,
-        // with the forward substitution folded in.  Inside a panel, step k publishes
-        // every row's column-k entry and gradient entry; with piv = A_kk and
-        // t_i = A_ik / piv for rows i > k (0 otherwise), A_ij -= t_i A_jk for the
-        // panel's later columns j and g_i -= t_i g_k; A_ik is then scaled to L_ik.
-        // The finished panel updates the trailing tiles on the matrix cores.
-#pragma unroll
-        for (int K = 0; K < NT; ++K) {
-            float* PK = pan + panel_row0<NT>(K) * kPS;  // row r >= 16K at PK + (r - 16K) * kPS
-#pragma unroll
-            for (int I = K; I < NT; ++I) {
-                const int id = I * (I + 1) / 2 + K;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) PK[(16 * (I - K) + 4 * g4 + j) * kPS + q16] = acc[id][j];
-            }
-            wave_lds_fence();
-            const bool mine = (ln >= 16 * K) && (ln < B);
-            const int prow = mine ? ln - 16 * K : 0;
-            float p[16];
-#pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-                const float4 v = *reinterpret_cast<const float4*>(PK + prow * kPS + 4 * c4);
-                p[4 * c4 + 0] = mine ? v.x : 0.f;
-                p[4 * c4 + 1] = mine ? v.y : 0.f;
-                p[4 * c4 + 2] = mine ? v.z : 0.f;
-                p[4 * c4 + 3] = mine ? v.w : 0.f;
-            }
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (16 * K + c > ln) p[c] = 0.f;
-            wave_lds_fence();
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int k = 16 * K + kk;
-                // column k of the panel lives in register p[kk] across the lanes
-                const float piv = readlane(p[kk], k);
-                const float gk = readlane(g, k);
-                const float rs = (piv > 0.f) ? __builtin_amdgcn_rsqf(piv) : 0.f;
-                const float t = (ln > k) ? p[kk] * (rs * rs) : 0.f;
-                g = fmaf(-t, gk, g);
-#pragma unroll
-                for (int jj = kk + 1; jj < 16; ++jj) p[jj] = fmaf(-t, readlane(p[kk], 16 * K + jj), p[jj]);
-                p[kk] *= rs;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (mine) {
-#pragma unroll
-                for (int c4 = 0; c4 < 4; ++c4)
-                    *reinterpret_cast<float4*>(PK + prow * kPS + 4 * c4) =
-                        make_float4(p[4 * c4], p[4 * c4 + 1], p[4 * c4 + 2], p[4 * c4 + 3]);
-            }
-            wave_lds_fence();
-            // trailing tiles: A_IJ -= L_IK L_JK^T for K < J <= I
-            if (K + 1 < NT) {
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    float op[NT];
-#pragma unroll
-                    for (int I = K + 1; I < NT; ++I) op[I] = PK[(16 * (I - K) + q16) * kPS + 4 * s4 + g4];
-#pragma unroll
-                    for (int I = K + 1; I < NT; ++I)
-#pragma unroll
-                        for (int J = K + 1; J <= I; ++J) {
-                            const int id = I * (I + 1) / 2 + J;
-                            acc[id] = mfma4(-op[I], op[J], acc[id]);
-                        }
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        // diagonal of L for this lane's row, from the panel that holds it
-        const int pk = ln >> 4;
-        const int pbase = panel_row0<NT>(pk) - 16 * pk;
-        const float lii = pan[(ln < B ? pbase + ln : 0) * kPS + (ln & 15)];
-        const float dinv = (ln < B && lii > 0.f) ? 1.f / lii : 0.f;
-        const float mypiv = lii * lii;
-        // pivot check over the real (unpadded) coordinates
-        const bool real = (ln < B) && (my_col < A.bw);
-        float pmin = real ? mypiv : 3.0e38f;
-        float pmax = real ? mypiv : 0.f;
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) {
-            pmin = fminf(pmin, __shfl_xor(pmin, m));
-            pmax = fmaxf(pmax, __shfl_xor(pmax, m));
-        }
-        // identical in every lane after the reductions; made explicitly uniform so the
-        // row loop stays a uniform loop (its queue step needs the whole wave)
-        const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < A.tau * pmax)) ? 1 : 0);
-        if (bad) {
+        float w;
+        if (!ldl_solve<NT>(acc, g, pan, zero_lds, ln, A.tau, my_col, A.bw, w)) {
+            // a pivot was rejected: the row is redone in float64
             if (lane == 0) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
                 A.fb_list[pos] = r;
             }
             continue;
         }
-        g *= dinv;  // y = L^-1 grad
-        // Back substitution L^T x = y, 16 rows of L at a time from the last band;
-        // lane i reads L[k][i] of the band from the panel that holds column i.
-        const float gdinv = dinv;
-#pragma unroll
-        for (int K = NT - 1; K >= 0; --K) {
-            float lt[16];
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const bool ok = (pk <= K) && (ln <= 16 * K + jj) && (ln < B);
-                const int rowi = ok ? pbase + 16 * K + jj : 0;
-                const float v = pan[rowi * kPS + (ln & 15)];
-                lt[jj] = ok ? v : 0.f;
-            }
-#pragma unroll
-            for (int jj = 15; jj >= 0; --jj) {
-                const int k = 16 * K + jj;
-                const float xk = readlane(g * gdinv, k);
-                g = (ln == k) ? xk : ((ln < k) ? fmaf(-lt[jj], xk, g) : g);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        wave_lds_fence();
-        // g (lane p) = delta at block column colmap(p)
-        if (lane < B && my_col < A.bw) A.X[(size_t)r * A.d + A.p0 + my_col] -= g;
+        // w (lane p) = delta at block column colmap(p)
+        if (lane < B && my_col < A.bw) A.X[(size_t)r * A.d + A.p0 + my_col] -= w;
     }
 }
 
@@ -587,7 +641,7 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
                            dim3(256), 0, st, args);
     }
     if (s.nrows > 0) {
-        const size_t lds = sizeof(float) * rows_lds_floats<NT>();
+        const size_t lds = sizeof(float) * (rows_lds_floats<NT>() + kZeroFloats);
         hipLaunchKernelGGL((k_make_dtiles<NT, FULL>), dim3((ntiles<NT>() * 256 + 255) / 256), dim3(256), 0, st, args.Dmat,
                            args.dtiles);
         {
