@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
     ap.add_argument("--block", type=int, default=0, help="block size b (0: the workload's)")
+    ap.add_argument("--seg-len", type=int, default=0,
+                    help="observations per segment of long rows (0: the library default, 1024)")
+    ap.add_argument("--deal", choices=("auto", "static", "queue"), default="auto", help="row dealing of the row kernels")
     ap.add_argument("--autotune", action="store_true",
                     help="choose b, row dealing and segment length by measurement first (cached in --tune-cache)")
     ap.add_argument("--tune-cache", default=os.path.join("gpurun_out", "autotune.json"))
@@ -244,7 +247,7 @@ def main():
     log(f"[bench] generated in {time.time() - t0:.1f}s; building the index on the GPU")
     torch.cuda.set_device(0)
     prec = binding.IALS_PREC_BF16 if args.precision == "bf16" else binding.IALS_PREC_FP32
-    deal, seg_len, tuned = "auto", 0, None
+    deal, seg_len, tuned = args.deal, args.seg_len, None
     if args.autotune:
         from paper_2110_14044_amd import autotune
         tuned = autotune.tune(p, prec, cache_path=args.tune_cache, log=log)

@@ -70,7 +70,7 @@ enum { IALS_FLAG_GRAPH = 1u };
 /* Row dealing of the block-pass kernels (tuning; results do not depend on it):
  * IALS_FLAG_DEAL_QUEUE: wavefronts take rows from a shared atomic queue;
  * IALS_FLAG_DEAL_STATIC: rows are dealt round-robin in decreasing length order.
- * Neither: static when the side's mean row length is below 256, else the queue. */
+ * Neither: static. */
 enum { IALS_FLAG_DEAL_QUEUE = 2u, IALS_FLAG_DEAL_STATIC = 4u };
 
 typedef struct {

@@ -79,6 +79,7 @@ struct SweepArgs {
     int32_t rows_batch;   // 0: static round-robin rows; 1: rows from the shared queue
     double* fb_scratch;   // float64 Hessians of the wide-block fallback (one B x B per workgroup)
     int32_t seg_len;      // segment length of long rows
+    int32_t seg_group;    // a row's segment partials are summed in groups of this many (k_seg_group)
 };
 
 // One fold-in request as the fold-in kernel reads it (from device or pinned host memory).
@@ -214,6 +215,8 @@ size_t fold_ws_floats(const FoldShape& f, int64_t n);
 hipError_t launch_foldin(hipStream_t st, const FoldShape& f, const float* H, const float* G, float alpha0,
                          float lambda, float tau, int32_t passes, const FoldReq* reqs, int32_t m, int32_t* counters);
 size_t seg_part_floats_per_segment(int32_t B);
+// Group sums of segment partials (stride floats each) when A.seg_group > 1.
+void launch_seg_group(hipStream_t st, const SweepArgs& A, int32_t stride);
 size_t big_fallback_doubles(int32_t B);
 
 // Allocation helper that tracks the context's byte count and budget.

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "ials_internal.h"
 
@@ -134,9 +135,14 @@ __device__ inline void load_cur(const SweepArgs& A, const float* X, int i, int q
 // BF: the Hessian products take bfloat16 operands (one 16x16x16 MFMA per tile for the
 // four observations of every lane group, 16 in all); the gradient and the predictions
 // stay float32.
-template <int NT, bool FULL, bool TRANS, bool BF>
+template <int NT, bool FULL, bool TRANS, bool BF, int U = 4>
 __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
                                   floatx4* acc, float* gp, int lane) {
+    // U steps of 4 observations per batch.  A batch has no branches: its partner rows are
+    // all loaded before any is used (steps past the chunk load a valid row and contribute
+    // nothing, their weight being 0), so the loads of a batch are in flight together.
+    static_assert(U == 2 || U == 4 || U == 8, "batches of 2, 4 or 8 steps");
+    static_assert(!BF || U % 4 == 0, "a bfloat16 product takes four steps");
     const int q16 = lane & 15, g4 = lane >> 4;
     for (int64_t c0 = lo; c0 < hi; c0 += 64) {
         const int64_t k = c0 + lane;
@@ -152,89 +158,86 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
         }
         const int cnt = (int)std::min<int64_t>(64, hi - c0);
         const int nsteps = (cnt + 3) >> 2;
-        for (int st = 0; st < nsteps; st += 4) {
-            const int nv = std::min(4, nsteps - st);
-            float x[4][NT], xc[4][TRANS ? NT : 1];
-            float xa4[BF ? 4 : 1][NT];
+        for (int st = 0; st < nsteps; st += U) {
+            float x[U][NT], xc[U][TRANS ? NT : 1];
+            float xa4[BF ? U : 1][NT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u < nv) {
-                    const int i = __shfl(ci, 4 * (st + u) + g4);
-                    load_cols<NT, FULL>(A.Xo, A.d, i, A.p0, A.bw, q16, x[u]);
-                    if constexpr (TRANS) load_cur<NT>(A, A.Xo, i, q16, xc[u]);
-                }
+            for (int u = 0; u < U; ++u) {
+                const int i = __shfl(ci, (4 * (st + u) + g4) & 63);
+                load_cols<NT, FULL>(A.Xo, A.d, i, A.p0, A.bw, q16, x[u]);
+                if constexpr (TRANS) load_cur<NT>(A, A.Xo, i, q16, xc[u]);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u < nv) {
-                    const int src = 4 * (st + u) + g4;
-                    const bool valid = src < cnt;
-                    const float ck = __shfl(cv, src);
-                    const float yk = A.y ? __shfl(yv, src) : 1.f;
-                    // every lane takes part in the shuffles (a source lane must be active)
-                    const float ak_all = A.a ? __shfl(av, src) : 1.f;
-                    const float ak = valid ? ak_all : 0.f;
-                    float sp = 0.f;
+            for (int u = 0; u < U; ++u) {
+                const int src = 4 * (st + u) + g4;
+                const bool valid = src < cnt;
+                const float ck = __shfl(cv, src & 63);
+                const float yk = A.y ? __shfl(yv, src & 63) : 1.f;
+                const float ak_all = A.a ? __shfl(av, src & 63) : 1.f;
+                const float ak = valid ? ak_all : 0.f;
+                float sp = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
-                    sp = sum16(sp);
-                    float yh = ck + sp;
-                    if constexpr (TRANS) {
-                        float sc = 0.f;
+                for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
+                sp = sum16(sp);
+                float yh = ck + sp;
+                if constexpr (TRANS) {
+                    float sc = 0.f;
 #pragma unroll
-                        for (int t = 0; t < NT; ++t) sc = fmaf(xc[u][t], ownc[t], sc);
-                        sc = sum16(sc);
-                        yh = ck + sc;
-                        const int sk = __shfl(si, src);
-                        if (q16 == 0 && valid) A.cache[sk] = yh - sp;
-                    }
-                    const float rk = ak * (yh - yk);
-                    float xa[NT];
+                    for (int t = 0; t < NT; ++t) sc = fmaf(xc[u][t], ownc[t], sc);
+                    sc = sum16(sc);
+                    yh = ck + sc;
+                    const int sk = __shfl(si, src & 63);
+                    if (q16 == 0 && valid) A.cache[sk] = yh - sp;
+                }
+                const float rk = ak * (yh - yk);
+                float xa[NT];
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        gp[t] = fmaf(rk, x[u][t], gp[t]);
-                        xa[t] = ak * x[u][t];
-                    }
-                    if constexpr (BF) {
+                for (int t = 0; t < NT; ++t) {
+                    gp[t] = fmaf(rk, x[u][t], gp[t]);
+                    xa[t] = ak * x[u][t];
+                }
+                if constexpr (BF) {
 #pragma unroll
-                        for (int t = 0; t < NT; ++t) xa4[u][t] = xa[t];
-                    } else {
-                        int id = 0;
+                    for (int t = 0; t < NT; ++t) xa4[u][t] = xa[t];
+                } else {
+                    int id = 0;
 #pragma unroll
-                        for (int ti = 0; ti < NT; ++ti)
+                    for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-                            for (int tj = 0; tj <= ti; ++tj) {
-                                acc[id] = mfma4(xa[ti], x[u][tj], acc[id]);
-                                ++id;
-                            }
-                    }
-                } else if constexpr (BF) {
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        x[u][t] = 0.f;
-                        xa4[u][t] = 0.f;
-                    }
+                        for (int tj = 0; tj <= ti; ++tj) {
+                            acc[id] = mfma4(xa[ti], x[u][tj], acc[id]);
+                            ++id;
+                        }
                 }
             }
             if constexpr (BF) {
-                shortx4 pa[NT], pb[NT];
+                // four steps per bfloat16 product; a weight of 0 zeroes a padding step's terms
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    pa[t] = bf16x4(xa4[0][t], xa4[1][t], xa4[2][t], xa4[3][t]);
-                    pb[t] = bf16x4(x[0][t], x[1][t], x[2][t], x[3][t]);
-                }
-                int id = 0;
+                for (int h = 0; h < U; h += 4) {
+                    shortx4 pa[NT], pb[NT];
 #pragma unroll
-                for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj <= ti; ++tj) {
-                        acc[id] = mfma_bf16(pa[ti], pb[tj], acc[id]);
-                        ++id;
+                    for (int t = 0; t < NT; ++t) {
+                        pa[t] = bf16x4(xa4[h][t], xa4[h + 1][t], xa4[h + 2][t], xa4[h + 3][t]);
+                        pb[t] = bf16x4(x[h][t], x[h + 1][t], x[h + 2][t], x[h + 3][t]);
                     }
+                    int id = 0;
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj <= ti; ++tj) {
+                            acc[id] = mfma_bf16(pa[ti], pb[tj], acc[id]);
+                            ++id;
+                        }
+                }
             }
         }
     }
 }
+
+// Steps per batch of partner-row loads (4 rows a step): 4, or 2 when the pass also loads the
+// cache's block of every partner row in float32 (the registers of 4 would spill).
+template <bool TRANS, bool BF>
+constexpr int kBatchSteps = (TRANS && !BF) ? 2 : 4;
 
 // Own block values of row r: own[t] at block pi (this pass's column order),
 // ownc[t] at the cache's block (TRANS only).
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) gp[t] = 0.f;
         load_own<NT, FULL, TRANS>(A, A.seg_row[it], q16, own, ownc);
-        accumulate<NT, FULL, TRANS, BF>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
+        accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             gp[t] += __shfl_xor(gp[t], 16);
@@ -270,6 +273,47 @@ __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
             for (int t = 0; t < NT; ++t) P[NTL * 256 + 16 * t + q16] = gp[t];
         }
     }
+}
+
+// Group sums of segment partials.  A row of ns segments has ceil(ns / G) groups of G
+// consecutive segments (G = A.seg_group); the partial of each group's first segment becomes
+// the sum of the group's partials, element by element in segment order, so the row kernel
+// adds ceil(ns / G) partials instead of ns (one wavefront would otherwise sum a very long
+// row's partials alone).  Block (s, y) covers 1,024 floats of segment s's partial.
+__global__ __launch_bounds__(256) void k_seg_group(SweepArgs A, int32_t stride) {
+    const int s = blockIdx.x;
+    const int r = A.seg_row[s];
+    const int sf = A.seg_first[r];
+    if ((s - sf) % A.seg_group != 0) return;
+    const int64_t len = A.ptr[r + 1] - A.ptr[r];
+    const int ns = (int)((len + A.seg_len - 1) / A.seg_len);
+    const int end = std::min(s + A.seg_group, sf + ns);
+    const int e = (blockIdx.y * 256 + threadIdx.x) * 4;
+    if (end - s < 2 || e >= stride) return;
+    float* P = A.seg_part + (size_t)s * stride + e;
+    float4 v = *reinterpret_cast<const float4*>(P);
+    int t = s + 1;
+    // four partials loaded together, then added in segment order
+    for (; t + 4 <= end; t += 4) {
+        float4 w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const float4*>(A.seg_part + (size_t)(t + j) * stride + e);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v.x += w[j].x;
+            v.y += w[j].y;
+            v.z += w[j].z;
+            v.w += w[j].w;
+        }
+    }
+    for (; t < end; ++t) {
+        const float4 w = *reinterpret_cast<const float4*>(A.seg_part + (size_t)t * stride + e);
+        v.x += w.x;
+        v.y += w.y;
+        v.z += w.z;
+        v.w += w.w;
+    }
+    *reinterpret_cast<float4*>(P) = v;
 }
 
 // Blocked Cholesky storage: panel K (16 columns, rows 16K..B-1) of the factor L is
@@ -489,7 +533,7 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         if (sf < 0) {
             float own[NT], ownc[TRANS ? NT : 1];
             load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
-            accumulate<NT, FULL, TRANS, BF>(A, lo, hi, own, ownc, acc, gp, lane);
+            accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
@@ -497,13 +541,20 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
             }
         } else {
             const int ns = (int)((hi - lo + A.seg_len - 1) / A.seg_len);
-            for (int s = sf; s < sf + ns; ++s) {
+            for (int s = sf; s < sf + ns; s += A.seg_group) {
+                // the whole partial is loaded before it is added, so its loads are in flight together
                 const float* P = A.seg_part + (size_t)s * seg_stride<NT>();
+                floatx4 part[NTL];
+                float pg[NT];
 #pragma unroll
                 for (int id = 0; id < NTL; ++id)
-                    acc[id] += *reinterpret_cast<const floatx4*>(P + ((size_t)id * 64 + lane) * 4);
+                    part[id] = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(P + ((size_t)id * 64 + lane) * 4));
 #pragma unroll
-                for (int t = 0; t < NT; ++t) gp[t] += P[NTL * 256 + 16 * t + q16];
+                for (int t = 0; t < NT; ++t) pg[t] = __builtin_nontemporal_load(P + NTL * 256 + 16 * t + q16);
+#pragma unroll
+                for (int id = 0; id < NTL; ++id) acc[id] += part[id];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) gp[t] += pg[t];
             }
         }
         // lane p < B holds the gradient entry of position p
@@ -639,6 +690,7 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
         ProfScope ps(c, IALS_K_SEG_USER + sd);
         hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS, BF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
                            dim3(256), 0, st, args);
+        launch_seg_group(st, args, seg_stride<NT>());
     }
     if (s.nrows > 0) {
         const size_t lds = sizeof(float) * (rows_lds_floats<NT>() + kZeroFloats);
@@ -706,6 +758,12 @@ void launch_sweep_prec(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bo
 
 }  // namespace
 
+void launch_seg_group(hipStream_t st, const SweepArgs& A, int32_t stride) {
+    if (A.seg_group < 2 || A.nseg == 0) return;
+    hipLaunchKernelGGL(k_seg_group, dim3((unsigned)A.nseg, (unsigned)((stride + 1023) / 1024)), dim3(256), 0, st, A,
+                       stride);
+}
+
 size_t seg_part_floats_per_segment(int32_t B) {
     const int NT = B / 16;
     return (size_t)(NT * (NT + 1) / 2) * 256 + (size_t)B;
@@ -744,9 +802,13 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     A.cursors = c->cursors;
     A.counters = c->counters;
     A.tau = c->tau;
-    const int64_t avg = s.nrows > 0 ? c->nnz / s.nrows : 0;
-    A.rows_batch = (c->flags & IALS_FLAG_DEAL_QUEUE) ? 1 : ((c->flags & IALS_FLAG_DEAL_STATIC) ? 0 : (avg < 256 ? 0 : 1));
+    // static dealing unless asked otherwise: a row's work is bounded (rows longer than a
+    // segment add a few group partials), and the queue's atomics cost more than its balance gains
+    A.rows_batch = (c->flags & IALS_FLAG_DEAL_QUEUE) ? 1 : 0;
     A.seg_len = c->seg_len;
+    // sqrt(ns) groups of sqrt(ns) segments for the longest row once it has more than 8 segments
+    const int64_t max_ns = (s.max_len + c->seg_len - 1) / c->seg_len;
+    A.seg_group = max_ns > 8 ? (int32_t)std::ceil(std::sqrt((double)max_ns)) : 1;
     const bool trans = blk != c->cur_block;
     if (c->B > 64)
         launch_sweep_big(c, A, s, sd, trans);

@@ -329,14 +329,19 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
             }
         } else {
             const int ns = (int)((hi - lo + A.seg_len - 1) / A.seg_len);
-            for (int s = sf; s < sf + ns; ++s) {
+            for (int s = sf; s < sf + ns; s += A.seg_group) {
+                // this wavefront's tiles of the partial are loaded before they are added
                 const float* P = A.seg_part + (size_t)s * big_seg_stride<NT>();
+                floatx4 part[NT + 1];
 #pragma unroll
                 for (int m = 0; m <= NT; ++m) {
                     int I, J;
                     tile_of(m, I1, NT, I, J);
-                    acc[m] += *reinterpret_cast<const floatx4*>(P + ((size_t)tile_id(I, J) * 64 + lane) * 4);
+                    part[m] = __builtin_nontemporal_load(
+                        reinterpret_cast<const floatx4*>(P + ((size_t)tile_id(I, J) * 64 + lane) * 4));
                 }
+#pragma unroll
+                for (int m = 0; m <= NT; ++m) acc[m] += part[m];
                 if (lead) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) gp[t] += P[NTL * 256 + 16 * t + q16];
@@ -597,6 +602,7 @@ void launch_big_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int s
         ProfScope ps(c, IALS_K_SEG_USER + sd);
         hipLaunchKernelGGL((k_seg_big<NT, TRANS, BF>), dim3(std::min<unsigned>((unsigned)c->num_cu * 4, (unsigned)s.nseg)),
                            dim3(threads), 0, st, args);
+        launch_seg_group(st, args, big_seg_stride<NT>());
     }
     if (s.nrows > 0) {
         const size_t lds = sizeof(float) * L::TOTAL;

@@ -120,6 +120,17 @@ def test_long_rows_split_into_segments():
     assert st["segments_item"] > 0 and st["long_rows_item"] > 0
 
 
+@pytest.mark.parametrize("b", [32, 64])
+def test_long_rows_in_segment_groups(b):
+    # segments of 256 observations: the longest item row (~2,400 observations) has 10
+    # segments, which are summed in groups of ceil(sqrt(10)) = 4 (the last group ragged)
+    p = synth.small_problem(52 + b, 3000, 120, 60_000, 64, b, labels=True, zipf_s=0.8, std=0.1)
+    lens = np.bincount(p.item, minlength=p.num_items)
+    assert -(-lens.max() // 256) > 8
+    st = _epoch_check(p, 1, 1e-4, 1e-6, seg_len=256)
+    assert st["segments_item"] > 0 and st["long_rows_item"] > 0
+
+
 def test_forced_float64_fallback_matches():
     p = synth.make_problem("tiny")
     st = _epoch_check(p, 1, 1e-4, 1e-6, chol_fallback_ratio=1.0)

@@ -43,6 +43,16 @@ def test_wide_long_rows_in_segments(b):
     assert st["segments_item"] > 0 and st["long_rows_item"] > 0
 
 
+def test_wide_long_rows_in_segment_groups():
+    # segments of 256 observations: the longest item row has more than 8 segments, so the
+    # partials are summed in groups before the row kernel adds them
+    p = synth.small_problem(325, 3000, 400, 120_000, 256, 128, labels=True, zipf_s=0.8, std=0.1)
+    lens = np.bincount(p.item, minlength=p.num_items)
+    assert -(-lens.max() // 256) > 8
+    st = _epoch_check(p, 1, 1e-4, 1e-6, seg_len=256)
+    assert st["segments_item"] > 0 and st["long_rows_item"] > 0
+
+
 @pytest.mark.parametrize("b", [128, 256])
 def test_wide_forced_float64_fallback(b):
     p = synth.small_problem(330 + b, 400, 300, 5000, 256, b, labels=True, std=0.1)
