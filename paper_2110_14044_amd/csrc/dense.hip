@@ -206,6 +206,71 @@ __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const fl
             }
 }
 
+// The same partial on full 64 x 64 tiles with 16-byte loads, for d a multiple of 64 and a
+// block of a multiple of 64 columns fully inside the row: lane q16 loads columns
+// 4 q16 .. 4 q16 + 3 of a row, so MFMA tile j holds the columns congruent to j mod 4 (row m
+// of tile ft is f = f0 + 4 m + ft, column n of tile qt is q = q0 + 4 n + qt).  The four
+// wavefronts of a block take interleaved groups of 16 rows of the chunk; their partials are
+// added in LDS in wavefront order, so one partial per block is written.
+__global__ __launch_bounds__(256, 3) void k_gram_vec(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
+                                                  int32_t ncols, int32_t rows_per_chunk, float* __restrict__ part) {
+    __shared__ floatx4 red[3][16][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int f0 = blockIdx.x * 64, q0 = blockIdx.y * 64;
+    const int64_t r0 = (int64_t)blockIdx.z * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* xa = X + f0 + 4 * q16;
+    const float* xb = X + p0 + q0 + 4 * q16;
+    for (int64_t rb = r0 + 16 * wave; rb < r1; rb += 64) {
+        float4 a[4], b[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t r = rb + 4 * s + g4;
+            const int64_t rr = r < r1 ? r : r0;  // rows past the chunk: a valid row with a zero weight
+            a[s] = *reinterpret_cast<const float4*>(xa + (size_t)rr * d);
+            b[s] = *reinterpret_cast<const float4*>(xb + (size_t)rr * d);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bool in = rb + 4 * s + g4 < r1;
+            const float av[4] = {in ? a[s].x : 0.f, in ? a[s].y : 0.f, in ? a[s].z : 0.f, in ? a[s].w : 0.f};
+            const float bv[4] = {b[s].x, b[s].y, b[s].z, b[s].w};
+#pragma unroll
+            for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+                for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = mfma4(av[ft], bv[qt], acc[ft][qt]);
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) red[wave - 1][4 * ft + qt][lane] = acc[ft][qt];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) acc[ft][qt] += red[w][4 * ft + qt][lane];
+    float* out = part + (size_t)blockIdx.z * d * ncols + q0 + 4 * q16;
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int f = f0 + 4 * (4 * g4 + j) + ft;
+            *reinterpret_cast<float4*>(out + (size_t)f * ncols) =
+                make_float4(acc[ft][0][j], acc[ft][1][j], acc[ft][2][j], acc[ft][3][j]);
+        }
+}
+
 // out[e] = sum over chunks of part[c][e] in float64.  A block owns 16 outputs; its
 // 16 thread rows each sum every 16th chunk, and the 16 partial sums of an
 // output are then added in a fixed order.
@@ -279,6 +344,62 @@ __global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, int32_t B, 
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = r0 + 16 * rt + 4 * g4 + j;
+                const int q = qb + 16 * t + q16;
+                if (r < n)
+                    R0[(size_t)r * B + q] =
+                        (q < bw) ? fmaf(alpha0, acc[rt][t][j], lambda * X[(size_t)r * d + p0 + q]) : 0.f;
+            }
+}
+
+// The same with 16-byte loads along f, for d a multiple of 16 and B a multiple of 64: lane
+// (q16, g4) loads f = fb + 4 g4 .. fb + 4 g4 + 3 of its row, and k-step s of a 16-wide f block
+// takes f = fb + 4 g4 + s (G is read in the same order, so the product is unchanged).  One
+// wavefront per 64 rows x 64 columns starting at column 64 * blockIdx.y.
+__global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
+                                                   const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
+                                                   float lambda, float* __restrict__ R0) {
+    const int wave = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int qb = 64 * blockIdx.y;
+    const int64_t r0 = (int64_t)wave * 64;
+    if (r0 >= n) return;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* xr[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const int64_t r = r0 + 16 * rt + q16;
+        xr[rt] = X + (size_t)(r < n ? r : r0) * d + 4 * g4;  // rows past n: a valid row, never written
+    }
+    const float* gc = G + (size_t)(4 * g4) * B + qb + q16;
+    for (int fb = 0; fb < d; fb += 16) {
+        float4 a[4];
+        float b[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const float4*>(xr[rt] + fb);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[s][t] = gc[(size_t)(fb + s) * B + 16 * t];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const float av = s == 0 ? a[rt].x : (s == 1 ? a[rt].y : (s == 2 ? a[rt].z : a[rt].w));
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(av, b[s][t], acc[rt][t]);
+            }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t r = r0 + 16 * rt + 4 * g4 + j;
@@ -438,6 +559,13 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
+    if (!bf16 && d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0) {
+        // full 64 x 64 tiles with 16-byte loads (the tile grid is the same)
+        hipLaunchKernelGGL(k_gram_vec, grid, dim3(256), 0, st, n, d, X, p0, ncols, rows, part);
+        const int64_t count = (int64_t)d * ncols;
+        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)chunks, count, out);
+        return;
+    }
 #define IALS_GRAM(Q, BFV) hipLaunchKernelGGL((k_gram_part<Q, BFV>), grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part)
     if (bf16) {
         if (QT == 4) IALS_GRAM(4, true);
@@ -467,6 +595,11 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
     if (n == 0) return;
     const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
     const int B = c->B;
+    if (B % 64 == 0 && c->d % 16 == 0) {
+        hipLaunchKernelGGL(k_dense_vec, dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X, c->G, p0,
+                           bw, c->alpha0, c->lambda, c->R0);
+        return;
+    }
 #define IALS_DENSE(NTV, GY)                                                                                      \
     hipLaunchKernelGGL(k_dense<NTV>, dim3(grid, GY), dim3(256), 0, c->stream, n, c->d, B, X, c->G, p0, bw,       \
                        c->alpha0, c->lambda, c->R0)
