@@ -116,6 +116,63 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
     }
 }
 
+// The same for d = 256 J (J >= 2) with the whole wavefront on one observation: lane l
+// holds w_u[f] for f = 4 l + 256 j (j < J) and loads the same columns of h_i, UB observations
+// at a time with all their loads in flight, then each dot product is summed over the wave.
+template <int J, int UB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_predict_wide(int32_t U, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col, const float* __restrict__ W,
+                                                      const float* __restrict__ H, int32_t p0, int32_t bw, bool inside,
+                                                      const float* __restrict__ base, float* __restrict__ out) {
+    constexpr int D = 256 * J;
+    const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (u >= U) return;
+    float4 w[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        float4 v = *reinterpret_cast<const float4*>(W + (size_t)u * D + 4 * lane + 256 * j);
+        const int f = 4 * lane + 256 * j;
+        v.x = ((f + 0 >= p0 && f + 0 < p0 + bw) == inside) ? v.x : 0.f;
+        v.y = ((f + 1 >= p0 && f + 1 < p0 + bw) == inside) ? v.y : 0.f;
+        v.z = ((f + 2 >= p0 && f + 2 < p0 + bw) == inside) ? v.z : 0.f;
+        v.w = ((f + 3 >= p0 && f + 3 < p0 + bw) == inside) ? v.w : 0.f;
+        w[j] = v;
+    }
+    const int64_t lo = ptr[u], hi = ptr[u + 1];
+    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+        const int64_t k = c0 + lane;
+        const int ci = (k < hi) ? col[k] : 0;
+        const int cnt = (int)min((int64_t)64, hi - c0);
+        float mine = 0.f;  // lane t keeps the prediction of observation c0 + t
+        for (int t0 = 0; t0 < cnt; t0 += UB) {
+            float4 h[UB][J];
+#pragma unroll
+            for (int v = 0; v < UB; ++v) {
+                const int i = __shfl(ci, (t0 + v) & 63);  // past the chunk: a valid row, result unused
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * D + 4 * lane + 256 * j);
+            }
+#pragma unroll
+            for (int v = 0; v < UB; ++v) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    s = fmaf(w[j].x, h[v][j].x, s);
+                    s = fmaf(w[j].y, h[v][j].y, s);
+                    s = fmaf(w[j].z, h[v][j].z, s);
+                    s = fmaf(w[j].w, h[v][j].w, s);
+                }
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+                if (lane == t0 + v) mine = s;
+            }
+        }
+        if (lane < cnt) out[c0 + lane] = inside ? base[c0 + lane] + mine : mine;
+    }
+}
+
 // Partial Gramian of one row chunk: part[chunk][f][q] = sum_{r in chunk} X[r][f] X[r][p0+q]
 // for f < d, q < ncols (columns q >= bw are zero).  Block = one wavefront owning a
 // 64 x (16*QT) output tile (4 x QT MFMA tiles).  BF: bfloat16 operands (16 rows per
@@ -544,6 +601,15 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
     else if (c->d == 256)
         hipLaunchKernelGGL(k_predict_rows<4>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
                            bw, inside, c->yhat, out);
+    else if (c->d == 512)
+        hipLaunchKernelGGL((k_predict_wide<2, 4>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
+                           p0, bw, inside, c->yhat, out);
+    else if (c->d == 1024)
+        hipLaunchKernelGGL((k_predict_wide<4, 4>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
+                           p0, bw, inside, c->yhat, out);
+    else if (c->d == 2048)
+        hipLaunchKernelGGL((k_predict_wide<8, 2>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
+                           p0, bw, inside, c->yhat, out);
     else
         hipLaunchKernelGGL(k_predict, dim3(g), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col, c->W, c->H, p0, bw,
                            inside, c->yhat, out);

@@ -52,6 +52,23 @@ def test_predictions_gramian_and_loss_at_start():
     tr.close()
 
 
+@pytest.mark.parametrize("d,b", [(256, 64), (512, 64), (1024, 128), (2048, 64), (320, 64)])
+def test_predictions_and_gramians_at_width(d, b):
+    # each kernel family at its widths: a wavefront per observation for d = 512 / 1024 / 2048,
+    # 16 lanes per observation for d = 256, the generic kernel for d = 320; the Gramians on
+    # full 64 x 64 tiles (d a multiple of 64)
+    p = synth.small_problem(90 + d, 300, 200, 5000, d, b, std=0.1)
+    tr = gpu_trainer(p)
+    csr, _, _ = oracle_setup(p)
+    e = rel(tr.predictions(), oracle.predict(csr, p.W0, p.H0))
+    say(f"d={d}: predictions {e:.1e}")
+    assert e < 1e-6
+    for which, X in ((0, p.W0), (1, p.H0)):
+        assert rel(host(tr.gramian(which, -1)), oracle.gramian(X)) < 1e-5
+        assert rel(host(tr.gramian(which, 1)), oracle.gramian(X, b, b)) < 1e-5
+    tr.close()
+
+
 def _one_pass_check(p, side, blk, tol):
     tr = gpu_trainer(p)
     csr, ys, as_ = oracle_setup(p)
