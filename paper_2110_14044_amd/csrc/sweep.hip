@@ -345,29 +345,6 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
 // Zero rows read by the back substitution in place of panel rows a lane does not use.
 constexpr int kZeroFloats = 16 * kPS;
 
-// p += t * (lane J of this lane's 16-lane row of D): v_fmac_f32 with a DPP row_newbcast
-// source operand.  The first update of a step begins with two wait states, as a DPP read
-// of a VGPR that a VALU instruction has just written requires; the updates of one step are
-// volatile so they keep their order and D is not rewritten between them.
-template <int J, bool FIRST>
-__device__ inline void fmac_rowbcast(float& p, float D, float t) {
-    if constexpr (FIRST)
-        asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-                     : "+v"(p)
-                     : "v"(D), "v"(t), "i"(J));
-    else
-        asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-                     : "+v"(p)
-                     : "v"(D), "v"(t), "i"(J));
-}
-// Columns JJ..15 of one elimination step: p[jj] += D(row lane jj) * t.
-template <int JJ, bool FIRST>
-__device__ inline void eliminate_cols(float* p, float D, float t) {
-    if constexpr (JJ < 16) {
-        fmac_rowbcast<JJ, FIRST>(p[JJ], D, t);
-        eliminate_cols<JJ + 1, false>(p, D, t);
-    }
-}
 // Steps KK..15 of panel K (see ldl_solve).  src: ds_bpermute address of the lane of row
 // group K in this lane's row position; lk = this lane's row - 16K (-1 - 16K past the block).
 template <int K, int KK>

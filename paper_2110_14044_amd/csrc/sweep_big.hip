@@ -105,7 +105,11 @@ __device__ inline void tile_of(int m, int I1, int NT, int& I, int& J) {
 // the cache entries to this pass's block.  The gathered values go through this wave's
 // LDS staging area (NT x 64 floats, or NT x 64 packed bfloat16 quadruples) so that a
 // tile's column operand is addressed by its index.
-template <int NT, bool TRANS, bool BF>
+// Steps of 4 observations per batch of partner-row loads (registers: UB x NT x (1 + TRANS)).
+template <int NT, bool TRANS>
+constexpr int kBigBatch = NT == 8 ? (TRANS ? 2 : 4) : 1;
+
+template <int NT, bool TRANS, bool BF, int UB = kBigBatch<NT, TRANS>>
 __device__ void big_accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
                                int I1, floatx4* acc, float* gp, bool lead, int lane, float* stage) {
     const int q16 = lane & 15, g4 = lane >> 4;
@@ -130,56 +134,64 @@ __device__ void big_accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const
 #pragma unroll
                 for (int t = 0; t < NT; ++t) pb[t] = shortx4{0, 0, 0, 0};
             }
+            // UB steps at a time with all their partner rows loaded first; steps past the
+            // chunk load a valid row and weigh 0 (no branches, so the loads are in flight together)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (st + u >= nsteps) break;
-                float x[NT];
-                const int src = 4 * (st + u) + g4;
-                const bool valid = src < cnt;
-                const int i = __shfl(ci, src);
-                load_block<NT>(A.Xo, A.d, i, A.p0, A.bw, q16, x);
-                const float ck = __shfl(cv, src);
-                const float yk = A.y ? __shfl(yv, src) : 1.f;
-                const float ak_all = A.a ? __shfl(av, src) : 1.f;
-                const float ak = valid ? ak_all : 0.f;
-                float sp = 0.f;
+            for (int u0 = 0; u0 < 4; u0 += UB) {
+                float xb[UB][NT], xcb[UB][TRANS ? NT : 1];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) sp = fmaf(x[t], own[16 * t + q16], sp);
-                sp = sum16(sp);
-                float yh = ck + sp;
-                if constexpr (TRANS) {
-                    float xc[NT];
-                    load_block<NT>(A.Xo, A.d, i, A.pc, A.bwc, q16, xc);
-                    float sc = 0.f;
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) sc = fmaf(xc[t], ownc[16 * t + q16], sc);
-                    sc = sum16(sc);
-                    yh = ck + sc;
-                    const int sk = __shfl(si, src);
-                    if (lead && q16 == 0 && valid) A.cache[sk] = yh - sp;
+                for (int uu = 0; uu < UB; ++uu) {
+                    const int i = __shfl(ci, (4 * (st + u0 + uu) + g4) & 63);
+                    load_block<NT>(A.Xo, A.d, i, A.p0, A.bw, q16, xb[uu]);
+                    if constexpr (TRANS) load_block<NT>(A.Xo, A.d, i, A.pc, A.bwc, q16, xcb[uu]);
                 }
-                const float rk = ak * (yh - yk);
-                if (lead) {
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) gp[t] = fmaf(rk, x[t], gp[t]);
-                }
-                const float xa1 = ak * pick<NT>(x, I1);
-                const float xa2 = ak * pick<NT>(x, I2);
-                if constexpr (BF) {
-                    pa1[u] = bf16s(xa1);
-                    pa2[u] = bf16s(xa2);
+                for (int uu = 0; uu < UB; ++uu) {
+                    const int u = u0 + uu;
+                    const float* x = xb[uu];
+                    const int src = 4 * (st + u) + g4;
+                    const bool valid = src < cnt;
+                    const float ck = __shfl(cv, src & 63);
+                    const float yk = A.y ? __shfl(yv, src & 63) : 1.f;
+                    const float ak_all = A.a ? __shfl(av, src & 63) : 1.f;
+                    const float ak = valid ? ak_all : 0.f;
+                    float sp = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) pb[t][u] = bf16s(x[t]);
-                } else {
+                    for (int t = 0; t < NT; ++t) sp = fmaf(x[t], own[16 * t + q16], sp);
+                    sp = sum16(sp);
+                    float yh = ck + sp;
+                    if constexpr (TRANS) {
+                        float sc = 0.f;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) stage[t * 64 + lane] = x[t];
-                    wave_fence();
-#pragma unroll
-                    for (int m = 0; m <= NT; ++m) {
-                        const int J = m <= I1 ? m : m - I1 - 1;
-                        acc[m] = mfma4(m <= I1 ? xa1 : xa2, stage[J * 64 + lane], acc[m]);
+                        for (int t = 0; t < NT; ++t) sc = fmaf(xcb[uu][t], ownc[16 * t + q16], sc);
+                        sc = sum16(sc);
+                        yh = ck + sc;
+                        const int sk = __shfl(si, src & 63);
+                        if (lead && q16 == 0 && valid) A.cache[sk] = yh - sp;
                     }
-                    wave_fence();
+                    const float rk = ak * (yh - yk);
+                    if (lead) {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) gp[t] = fmaf(rk, x[t], gp[t]);
+                    }
+                    const float xa1 = ak * pick<NT>(x, I1);
+                    const float xa2 = ak * pick<NT>(x, I2);
+                    if constexpr (BF) {
+                        pa1[u] = bf16s(xa1);
+                        pa2[u] = bf16s(xa2);
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) pb[t][u] = bf16s(x[t]);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) stage[t * 64 + lane] = x[t];
+                        wave_fence();
+#pragma unroll
+                        for (int m = 0; m <= NT; ++m) {
+                            const int J = m <= I1 ? m : m - I1 - 1;
+                            acc[m] = mfma4(m <= I1 ? xa1 : xa2, stage[J * 64 + lane], acc[m]);
+                        }
+                        wave_fence();
+                    }
                 }
             }
             if constexpr (BF) {
@@ -275,17 +287,102 @@ __device__ inline floatx4 mm_pqt(floatx4 c, const float* P, const float* Q, floa
     return c;
 }
 
+// c -= (P diag(pv)) Q^T for 16 x 16 row-major tiles P, Q (pv: the 16 pivots of P's columns)
+__device__ inline floatx4 mm_pdqt(floatx4 c, const float* P, const float* Q, const float* pv, int lane) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int o = (lane & 15) * 16 + 4 * s + (lane >> 4);
+        c = mfma4(-P[o] * pv[4 * s + (lane >> 4)], Q[o], c);
+    }
+    return c;
+}
+
+// Step KK..15 of panel K for NH = B / 64 rows per lane (row 64 h + lane in p[h]); see
+// big_panel.  src: ds_bpermute address of this lane's position in row group K & 3.
+template <int NH, int KK>
+__device__ inline void big_steps(float (*p)[16], float* g, float* pvl, const float* lk, int K, int src, int lane) {
+    if constexpr (KK < 16) {
+        const int hK = K >> 2, l0 = 16 * (K & 3);
+        float v = p[0][KK], gv = g[0];
+#pragma unroll
+        for (int h = 1; h < NH; ++h) {
+            v = (hK == h) ? p[h][KK] : v;
+            gv = (hK == h) ? g[h] : gv;
+        }
+        const float piv = readlane(v, l0 + KK);
+        if (lane == 0) pvl[16 * K + KK] = piv;
+        const float nr = __builtin_amdgcn_rcpf(-piv);
+        float tn[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) tn[h] = p[h][KK] * nr * __builtin_amdgcn_fmed3f(lk[h] - (float)KK, 0.f, 1.f);
+        if constexpr (KK < 15) {
+            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
+            eliminate_cols<KK + 1, true>(p[0], D, tn[0]);
+#pragma unroll
+            for (int h = 1; h < NH; ++h) eliminate_cols<KK + 1, false>(p[h], D, tn[h]);
+        }
+        const float gk = readlane(gv, l0 + KK);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            g[h] = fmaf(tn[h], gk, g[h]);
+            p[h][KK] = tn[h];
+        }
+        big_steps<NH, KK + 1>(p, g, pvl, lk, K, src, lane);
+    }
+}
+
+// Panel K of the LDL^T factorisation (wave 0): the rows 16K .. B-1 of tile column K go to
+// a lane per row, each step k takes piv = A_kk, t_i = A_ik / piv for the rows below k,
+// g_i -= t_i g_k and A_ij -= t_i A_jk for the panel's later columns (column k of the
+// diagonal tile copied from its lanes and read with a row broadcast), and the rows are
+// written back holding -t (zeros on and above the diagonal); the pivots go to pvl.
+template <int NT>
+__device__ inline void big_panel(float* mat, float* pvl, float* g, int lane, int K) {
+    constexpr int NH = NT / 4;
+    float p[NH][16];
+    float lk[NH];
+    bool mine[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const int r = 64 * h + lane;
+        mine[h] = r >= 16 * K;
+        const float* src = mine[h] ? mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16 : mat;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const float4 v = *reinterpret_cast<const float4*>(src + 4 * c4);
+            p[h][4 * c4 + 0] = v.x;
+            p[h][4 * c4 + 1] = v.y;
+            p[h][4 * c4 + 2] = v.z;
+            p[h][4 * c4 + 3] = v.w;
+        }
+        lk[h] = (float)(r - 16 * K);
+    }
+    big_steps<NH, 0>(p, g, pvl, lk, K, (16 * (K & 3) + (lane & 15)) * 4, lane);
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const int r = 64 * h + lane;
+        if (mine[h]) {
+            float* dst = mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16;
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                *reinterpret_cast<float4*>(dst + 4 * c4) =
+                    make_float4(p[h][4 * c4], p[h][4 * c4 + 1], p[h][4 * c4 + 2], p[h][4 * c4 + 3]);
+        }
+    }
+}
+
 template <int NT, bool TRANS, bool BF>
 __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
     using L = BigLds<NT>;
-    constexpr int B = L::B, NW = L::NW, NTL = L::NTL;
+    constexpr int B = L::B, NTL = L::NTL, NH = B / 64;
     extern __shared__ __align__(16) float lds_big[];
     const int lane0 = threadIdx.x & 63;
     const int wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     static_assert(BigLds<NT>::NW * NT * 128 <= BigLds<NT>::NTL * 256, "staging fits in the matrix region");
     float* mat = lds_big + L::MAT;
     float* gl = lds_big + L::G;
-    float* spart = lds_big + L::SP;
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) lds_big[L::YP + e] = 0.f;
+    __syncthreads();
 
     for (int it = blockIdx.x; it < A.nrows; it += gridDim.x) {
         const int r = A.order[it];
@@ -298,8 +395,6 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
         asm volatile("" : "+s"(I1));
         const int q16 = lane & 15, g4 = lane >> 4, I2 = NT - 1 - I1;
         const bool lead = I1 == 0;
-        float* yp = lds_big + L::YP + I1 * 256;
-        float* xw = lds_big + L::XW + I1 * B;
         floatx4 acc[NT + 1];
         float gp[NT];
         const float* Dm = A.Dmat;
@@ -361,74 +456,21 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
         }
         __syncthreads();
 
-        // blocked Cholesky with the forward substitution folded in
-        float pmin = 3.0e38f, pmax = 0.f;
-        const int i16 = lane & 15;
+        // Blocked LDL^T on the tiles in LDS with the forward substitution folded in.  Wave 0
+        // factors each 16-column panel with a lane per row (lane l holds rows l, 64 + l, ...);
+        // every wave then applies the panel to its own tiles on the matrix cores.
+        float* zero = lds_big + L::YP;  // 16 x 16 zeros (back substitution)
+        float* pvl = zero + 256;        // [B] pivots
+        float g[NH];
+        if (I1 == 0) {
+#pragma unroll
+            for (int h = 0; h < NH; ++h) g[h] = gl[64 * h + lane];
+        }
 #pragma unroll 1
         for (int K = 0; K < NT; ++K) {
-            float* TK = mat + tile_id(K, K) * 256;
-            float a[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) a[k] = TK[i16 * 16 + k];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const float piv = readlane(a[k], k);
-                if (16 * K + k < A.bw) {
-                    pmin = fminf(pmin, piv);
-                    pmax = fmaxf(pmax, piv);
-                }
-                const float rs = piv > 0.f ? __builtin_amdgcn_rsqf(piv) : 0.f;
-                const float l = a[k] * rs;
-                a[k] = l;
-#pragma unroll
-                for (int j = k + 1; j < 16; ++j) a[j] = fmaf(-l, readlane(l, j), a[j]);
-            }
-            // Y = L_KK^-1, lane j holding column j
-            float y[16];
-#pragma unroll
-            for (int ii = 0; ii < 16; ++ii) {
-                float s = 0.f;
-#pragma unroll
-                for (int k = 0; k < ii; ++k) s = fmaf(readlane(a[k], ii), y[k], s);
-                const float di = 1.f / readlane(a[ii], ii);
-                y[ii] = (ii < i16) ? 0.f : (ii == i16 ? di : -s * di);
-            }
-            // z_K = L_KK^-1 g_K, lane i holding z_i
-            float zi = gl[16 * K + i16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const float zk = readlane(zi, k) / readlane(a[k], k);
-                zi = (i16 > k) ? fmaf(-a[k], zk, zi) : (i16 == k ? zk : zi);
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int ii = 0; ii < 16; ++ii) yp[ii * 16 + lane] = y[ii];
-            }
-            wave_fence();
-            // owners of tile rows I > K: L_IK = A_IK Y^T and g_I -= L_IK z_K
-#pragma unroll 1
-            for (int pass = 0; pass < 2; ++pass) {
-                const int I = pass == 0 ? I1 : I2;
-                if (I <= K) continue;
-                float* P = mat + tile_id(I, K) * 256;
-                floatx4 c = mm_pqt(floatx4{0.f, 0.f, 0.f, 0.f}, P, yp, 1.f, lane);
-                wave_fence();
-                tile_store(P, c, lane);
-                const float zq = __shfl(zi, q16);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float s = sum16(c[j] * zq);
-                    if (q16 == 0) gl[16 * I + 4 * g4 + j] -= s;
-                }
-            }
+            if (I1 == 0) big_panel<NT>(mat, pvl, g, lane, K);
             __syncthreads();
-            // Y_KK and z_K are kept for the back substitution (tile (K,K) is no longer read)
-            if (lead && lane < 16) {
-#pragma unroll
-                for (int ii = 0; ii < 16; ++ii) TK[ii * 16 + lane] = y[ii];
-                gl[16 * K + lane] = zi;
-            }
-            // trailing tiles: A_IJ -= L_IK L_JK^T for K < J <= I
+            // trailing tiles: A_IJ -= L_IK diag(piv) L_JK^T for K < J <= I (the panel holds -L)
 #pragma unroll 1
             for (int pass = 0; pass < 2; ++pass) {
                 const int I = pass == 0 ? I1 : I2;
@@ -438,11 +480,32 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
                 for (int J = K + 1; J <= I; ++J) {
                     float* T = mat + tile_id(I, J) * 256;
                     floatx4 c = tile_load(T, lane);
-                    c = mm_pqt(c, LI, mat + tile_id(J, K) * 256, -1.f, lane);
+                    c = mm_pdqt(c, LI, mat + tile_id(J, K) * 256, pvl + 16 * K, lane);
                     tile_store(T, c, lane);
                 }
             }
             __syncthreads();
+        }
+        if (I1 == 0) {
+#pragma unroll
+            for (int h = 0; h < NH; ++h) gl[64 * h + lane] = g[h];
+        }
+        __syncthreads();
+        // pivot check over the real coordinates (every wave, from LDS)
+        float pmin = 3.0e38f, pmax = 0.f;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int q = 64 * h + lane;
+            const float v = pvl[q];
+            if (q < A.bw) {
+                pmin = fminf(pmin, v);
+                pmax = fmaxf(pmax, v);
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            pmin = fminf(pmin, __shfl_xor(pmin, m));
+            pmax = fmaxf(pmax, __shfl_xor(pmax, m));
         }
         const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < A.tau * pmax)) ? 1 : 0);
         if (bad) {
@@ -453,38 +516,43 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
             __syncthreads();
             continue;
         }
-        // back substitution L^T x = z, panel by panel from the last
+        if (I1 == 0) {
+            // w = D^-1 L^-1 g, then L^T x = w from the last column (see the narrow kernel)
+            float w[NH];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) w[h] = gl[64 * h + lane] * __builtin_amdgcn_rcpf(pvl[64 * h + lane]);
 #pragma unroll 1
-        for (int K = NT - 1; K >= 0; --K) {
-            float s = 0.f;  // lane: column q16 of tile column K, rows 4 g4 .. 4 g4 + 3
-#pragma unroll 1
-            for (int pass = 0; pass < 2; ++pass) {
-                const int I = pass == 0 ? I1 : I2;
-                if (I <= K) continue;
-                const float* P = mat + tile_id(I, K) * 256;
+            for (int K = NT - 1; K >= 0; --K) {
+                const float* rowp[NH];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) s = fmaf(P[(4 * g4 + j) * 16 + q16], xw[16 * I + 4 * g4 + j], s);
+                for (int h = 0; h < NH; ++h) {
+                    const int ti = 4 * h + (lane >> 4);  // tile column of this lane's row
+                    rowp[h] = (ti <= K) ? mat + tile_id(K, ti) * 256 + (lane & 15) : zero + (lane & 15);
+                }
+                float lt[NH][16];
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+#pragma unroll
+                    for (int jj = 0; jj < 16; ++jj) lt[h][jj] = rowp[h][jj * 16];
+                const int hk = K >> 2;
+                float wk = w[0];
+#pragma unroll
+                for (int h = 1; h < NH; ++h) wk = (hk == h) ? w[h] : wk;
+#pragma unroll
+                for (int jj = 15; jj >= 0; --jj) {
+                    const float xk = readlane(wk, 16 * (K & 3) + jj);
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) w[h] = fmaf(lt[h][jj], xk, w[h]);
+                    wk = w[0];
+#pragma unroll
+                    for (int h = 1; h < NH; ++h) wk = (hk == h) ? w[h] : wk;
+                }
             }
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            float* sp = spart + (K & 1) * NW * 16;
-            if (g4 == 0) sp[I1 * 16 + q16] = s;
-            __syncthreads();
-            // every wave: x_K = Y_KK^T (z_K - sum of the partials)
-            const float* TK = mat + tile_id(K, K) * 256;
-            float x = 0.f;
 #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                float t = gl[16 * K + rr];
-#pragma unroll
-                for (int w = 0; w < NW; ++w) t -= sp[w * 16 + rr];
-                x = fmaf(TK[rr * 16 + i16], t, x);
+            for (int h = 0; h < NH; ++h) {
+                const int q = 64 * h + lane;
+                if (q < A.bw) A.X[(size_t)r * A.d + A.p0 + q] -= w[h];
             }
-            if (lane < 16) xw[16 * K + lane] = x;
-            wave_fence();
-        }
-        if (lead) {
-            for (int q = lane; q < A.bw; q += 64) A.X[(size_t)r * A.d + A.p0 + q] -= xw[q];
         }
         __syncthreads();
     }
