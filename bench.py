@@ -42,7 +42,7 @@ def rows_work(lengths, b, trans_fraction):
     """Algorithmic FLOPs and bytes of one row-kernel launch.  Rows of <= SEG_LEN observations are
     accumulated there (per observation: rank-1 Hessian update 2 b^2, gradient 2 b, prediction
     dot product 2 b, plus 2 b more when the pass moves the cache to a new block); every row is
-    solved (Cholesky b^3/3 + two triangular solves 2 b^2) and updated.  trans_fraction is the
+    solved (LDL^T factorisation b^3/3 + two triangular solves 2 b^2) and updated.  trans_fraction is the
     share of launches that move the cache."""
     import numpy as np
     lengths = np.asarray(lengths, np.int64)
@@ -311,12 +311,38 @@ def main():
                  "rows_user_move": "k_sweep_rows<NT,.,true,.> (user pass that moves the prediction cache)",
                  "rows_item": "k_sweep_rows<NT,.,false,.> (item pass)"}[dom]
     roofline = {
-        "kernel": kname + ": gather + MFMA Hessian + blocked Cholesky + update",
+        "kernel": kname + ": gather + MFMA Hessian + blocked LDL^T solve + update",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": measured_traffic(dom, wl.name, p.block, args.precision),
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
         "avg_launch_ms": kern[dom]["avg_ms"],
         "algorithmic_GBps": round(bytes_ / avg_s / 1e9, 1),
+    }
+
+    # the Gramian (GEMM on the matrix cores) and the gather kernels, from the same timed epochs
+    bcols = ((p.block + 15) // 16) * 16
+    gram_flops = 2.0 * p.num_users * p.dim * bcols  # W^T W[:, pi] for an item pass
+    dense_flops = 2.0 * p.num_users * p.dim * bcols  # W G^pi for a user pass
+    pred_bytes = p.nnz * (4.0 * p.dim + 8) + 4.0 * p.num_users * p.dim
+    seg_nnz = int(li[li > SEG_LEN].sum())
+    seg_bytes = seg_nnz * (4.0 * p.block + 12)
+
+    def _rate(name, work, scale, peak, unit, what):
+        if name not in kern or kern[name]["avg_ms"] <= 0:
+            return None
+        a = work / (kern[name]["avg_ms"] / 1e3) / scale
+        return {"what": what, "achieved": round(a, 2), "peak": peak, "unit": unit, "frac": round(a / peak, 4),
+                "avg_launch_ms": kern[name]["avg_ms"]}
+    kernel_rates = {
+        "gramian_W": _rate("gram_item", gram_flops, 1e12, PEAK_FP32_MFMA, "TFLOP/s",
+                           "k_gram_vec + float64 split-K reduction + Dmat: W^T W[:, pi] per item pass"),
+        "dense_W": _rate("dense_user", dense_flops, 1e12, PEAK_FP32_MFMA, "TFLOP/s",
+                         "k_dense_vec: alpha0 W G^pi + lambda W_pi per user pass"),
+        "predict": _rate("predict", pred_bytes, 1e9, PEAK_HBM, "GB/s",
+                         "prediction recompute, algorithmic bytes (partner row, id, output per observation; "
+                         "W once); the L2 serves repeated partner rows, so frac can exceed what HBM sees"),
+        "seg_item": _rate("seg_item", seg_bytes, 1e9, PEAK_HBM, "GB/s",
+                          "item long-row segments, algorithmic gather bytes (partner block, id, slot, cache)"),
     }
 
     cpu = None
@@ -371,7 +397,7 @@ def main():
                    "epoch_s": epoch_s, "parallelism": "single GPU", "deal": deal, "seg_len": seg_len or 1024},
         "autotune": tuned,
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
-        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,
+        "roofline": roofline, "kernel_rates": kernel_rates, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,
     }
     tr.close()
     print(json.dumps(out))

@@ -82,9 +82,10 @@ typedef struct {
     float alpha0;               /* weight of the all-pairs term, >= 0 */
     float lambda;               /* L2 weight, > 0 */
     int32_t precision;          /* ials_precision */
-    float chol_fallback_ratio;  /* tau: a row whose float32 Cholesky pivots satisfy
-                                   min L_kk^2 < tau * max L_kk^2 (or any pivot <= 0)
-                                   is refactored in float64; <= 0 selects 1e-6 */
+    float chol_fallback_ratio;  /* tau: a row whose float32 pivots (the diagonal of D in
+                                   Hess = L D L^T, i.e. the squared Cholesky diagonal)
+                                   satisfy min < tau * max (or any pivot <= 0) is
+                                   refactored in float64; <= 0 selects 1e-6 */
     uint32_t flags;             /* IALS_FLAG_* bits */
     uint32_t seg_len;           /* rows longer than this are accumulated in segments of this many
                                    observations (split-K); a multiple of 64 in [256, 65536];
@@ -144,7 +145,7 @@ IALS_API ials_status ials_gramian(ials_ctx* ctx, int32_t which, int32_t block, f
  * for every user against the current H; side ITEM updates h_{i,pi} against the
  * current W.  Each row gets one Newton step on its block (sec. 4, eq. 8-9:
  * gradient from the cached yhat and the partial Gramian, Hessian from the
- * gathered partner sub-vectors), a Cholesky solve, the update and the yhat
+ * gathered partner sub-vectors), an LDL^T solve, the update and the yhat
  * patch.  yhat must be current (create, ials_epoch and this call keep it so).
  * Asynchronous.
  */
@@ -219,7 +220,7 @@ typedef enum {
     IALS_K_DENSE_ITEM = 4,
     IALS_K_SEG_USER = 5,      /* partial Hessians/gradients of long-row segments */
     IALS_K_SEG_ITEM = 6,
-    IALS_K_ROWS_USER = 7,     /* gather + Hessian + Cholesky + update + yhat patch per row */
+    IALS_K_ROWS_USER = 7,     /* gather + Hessian + LDL^T solve + update + yhat patch per row */
     IALS_K_ROWS_ITEM = 8,
     IALS_K_FALLBACK_USER = 9, /* float64 redo of rejected factorisations */
     IALS_K_FALLBACK_ITEM = 10,

@@ -221,6 +221,15 @@ __global__ void k_len_keys(const int64_t* __restrict__ ptr, int32_t nrows, int32
     nseg[r] = (len > seg_len) ? (int32_t)((len + seg_len - 1) / seg_len) : 0;
 }
 
+// Sort key of each segment: its first partner id (then the segment id, for a total order).
+__global__ void k_seg_keys(const int64_t* __restrict__ seg_lo, const int32_t* __restrict__ col, int32_t nseg,
+                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    keys[s] = ((uint64_t)(uint32_t)col[seg_lo[s]] << 32) | (uint32_t)s;
+    vals[s] = s;
+}
+
 __global__ void k_seg_fill(const int64_t* __restrict__ ptr, int32_t nrows, int32_t seg_len,
                            const int32_t* __restrict__ nseg_scan,
                            const int32_t* __restrict__ nseg, int32_t* __restrict__ seg_first,
@@ -398,6 +407,15 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         hipLaunchKernelGGL(k_seg_fill, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, c->seg_len, scan, nseg, s.seg_first,
                            s.seg_row, s.seg_lo, s.seg_hi);
         IALS_HIP_TRY(c, hipGetLastError());
+        // processing order of the segments: by first partner id, so that the segments in flight
+        // at one time gather from neighbouring partner rows (long rows' segments are narrow id
+        // ranges) and share the L2
+        if (total > 0) {
+            IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_order, sizeof(int32_t) * total));
+            hipLaunchKernelGGL(k_seg_keys, dim3(nblk(total, 256)), dim3(256), 0, st, s.seg_lo, s.col, total, keys, vals);
+            IALS_HIP_TRY(c, radix_sort(keys, vals, kalt, valt, total, 64, hist, sums, st));
+            IALS_HIP_TRY(c, hipMemcpyAsync(s.seg_order, vals, sizeof(int32_t) * total, hipMemcpyDeviceToDevice, st));
+        }
         // number of long rows
         if (nr > 0) {
             std::vector<int32_t> h_nseg(nr);

@@ -44,6 +44,7 @@ struct SideIndex {
     int32_t* seg_row = nullptr;   // [nseg]
     int64_t* seg_lo = nullptr;    // [nseg]
     int64_t* seg_hi = nullptr;    // [nseg]
+    int32_t* seg_order = nullptr; // [nseg] segments by their first partner id (processing order)
     int32_t nseg = 0;
     int32_t nlong = 0;
     int64_t max_len = 0;
@@ -70,6 +71,7 @@ struct SweepArgs {
     const int32_t* seg_row;
     const int64_t* seg_lo;
     const int64_t* seg_hi;
+    const int32_t* seg_order;  // processing order of the segments
     int32_t nseg;
     float* seg_part;
     int32_t* fb_list;

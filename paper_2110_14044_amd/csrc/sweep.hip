@@ -6,7 +6,7 @@
 //   yhat_k = c_k + <x_{r,pi}, T_k>               (c: prediction cache without block pi)
 //   Hess   = alpha0 G_pipi + lambda I + T^T diag(a) T   (MFMA f32 16x16x4, lower tiles only)
 //   grad   = R0[r] + T^T (a (yhat - y))          (R0 = alpha0 x_r G^pi + lambda x_{r,pi}, precomputed)
-//   delta  = Hess^-1 grad                         (blocked Cholesky on the accumulator tiles)
+//   delta  = Hess^-1 grad                         (blocked LDL^T on the accumulator tiles)
 //   x_{r,pi} -= delta
 //
 // The prediction cache holds, per observation, the prediction minus the part of
@@ -21,7 +21,8 @@
 // accumulates each segment's partial Hessian and gradient, the row kernel adds
 // them in segment order (a fixed order, so results are bitwise reproducible) and
 // solves.
-// A row whose float32 Cholesky pivots fall below tau * (largest pivot), or are
+// A row whose float32 pivots (the diagonal of D in Hess = L D L^T, the squares of the
+// Cholesky diagonal) fall below tau * (largest pivot), or are
 // not positive, is redone from scratch in float64 by k_sweep_fallback.
 //
 // Column order.  The MFMA position p = 16 t + m (tile t, lane m of a 16-lane
@@ -251,7 +252,8 @@ template <int NT, bool FULL, bool TRANS, bool BF>
 __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
     constexpr int NTL = ntiles<NT>();
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
-    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < A.nseg; it += gridDim.x * 4) {
+    for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < A.nseg; j += gridDim.x * 4) {
+        const int it = A.seg_order[j];
         floatx4 acc[NTL];
         float gp[NT], own[NT], ownc[TRANS ? NT : 1];
 #pragma unroll
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(256) void k_seg_group(SweepArgs A, int32_t stride) 
     *reinterpret_cast<float4*>(P) = v;
 }
 
-// Blocked Cholesky storage: panel K (16 columns, rows 16K..B-1) of the factor L is
+// Blocked factorisation storage: panel K (16 columns, rows 16K..B-1) of the factor L is
 // kept in LDS with row stride kPS; panels are packed one after another.
 constexpr int kPS = 16;
 template <int NT>
@@ -773,6 +775,7 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     A.seg_row = s.seg_row;
     A.seg_lo = s.seg_lo;
     A.seg_hi = s.seg_hi;
+    A.seg_order = s.seg_order;
     A.nseg = s.nseg;
     A.seg_part = c->seg_part;
     A.fb_list = c->fb_list;

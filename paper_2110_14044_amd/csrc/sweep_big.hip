@@ -13,15 +13,14 @@
 // per-segment partials instead (k_seg_big), summed in segment order.
 //
 // Factorisation: the tiles go to LDS (packed lower tiles, 256 floats each) and a
-// right-looking blocked Cholesky runs over them with rolled loops (the code stays
-// small): for panel K every wave factors and inverts the 16 x 16 diagonal tile
-// itself (Y = L_KK^-1) and forward-substitutes z_K = L_KK^-1 g_K; the owner of
-// each tile row I > K forms L_IK = A_IK Y^T on the matrix cores and updates g_I;
-// after a barrier every owner subtracts L_IK L_JK^T from its tiles (I, J), K < J <= I.
-// Back substitution L^T x = z goes panel by panel from the last: the owners'
-// partial sums L_IK^T x_I meet in LDS (one barrier per panel) and every wave forms
-// x_K = Y_KK^T (z_K - sum) itself.  A row whose pivots fail the ratio test is redone
-// in float64 by k_fallback_big.
+// blocked right-looking LDL^T runs over them, panel by panel: wave 0 takes the 16
+// columns of panel K with a lane per row (lane l holds rows l, 64 + l, ...), eliminates
+// them step by step with the forward substitution folded in (column k of the diagonal
+// tile is copied to every row group and read with a DPP row broadcast, so each update
+// is one fused multiply-add) and writes back -L with the pivots; after a barrier every
+// wave subtracts L_IK diag(piv) L_JK^T from its own tiles (I, J), K < J <= I, on the
+// matrix cores.  Wave 0 then solves L^T x = D^-1 z column by column from the last.  A
+// row whose pivots fail the ratio test is redone in float64 by k_fallback_big.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
