@@ -435,15 +435,25 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
         xr[rt] = X + (size_t)(r < n ? r : r0) * d + 4 * g4;  // rows past n: a valid row, never written
     }
     const float* gc = G + (size_t)(4 * g4) * B + qb + q16;
-    for (int fb = 0; fb < d; fb += 16) {
-        float4 a[4];
-        float b[4][4];
+    float4 a[4];
+    float b[4][4];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const float4*>(xr[rt] + fb);
+    for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const float4*>(xr[rt]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[s][t] = gc[(size_t)s * B + 16 * t];
+    for (int fb = 0; fb < d; fb += 16) {
+        // the next 16 columns' operands are loaded before this block is multiplied
+        const int fn = fb + 16 < d ? fb + 16 : fb;
+        float4 an[4];
+        float bn[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) an[rt] = *reinterpret_cast<const float4*>(xr[rt] + fn);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b[s][t] = gc[(size_t)(fb + s) * B + 16 * t];
+            for (int t = 0; t < 4; ++t) bn[s][t] = gc[(size_t)(fn + s) * B + 16 * t];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -452,6 +462,12 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(av, b[s][t], acc[rt][t]);
             }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = an[rt];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[s][t] = bn[s][t];
     }
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
@@ -626,10 +642,14 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
     if (!bf16 && d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0) {
-        // full 64 x 64 tiles with 16-byte loads (the tile grid is the same)
-        hipLaunchKernelGGL(k_gram_vec, grid, dim3(256), 0, st, n, d, X, p0, ncols, rows, part);
+        // full 64 x 64 tiles with 16-byte loads; four wavefronts per block, so a quarter of the
+        // blocks (and of the partials the reduction reads) for the same number of wavefronts
+        const int rv = chunk_rows_for(n, ft * qg, 512, 256);
+        const int64_t cv = std::max<int64_t>(1, (n + rv - 1) / rv);
+        hipLaunchKernelGGL(k_gram_vec, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d, X, p0,
+                           ncols, rv, part);
         const int64_t count = (int64_t)d * ncols;
-        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)chunks, count, out);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)cv, count, out);
         return;
     }
 #define IALS_GRAM(Q, BFV) hipLaunchKernelGGL((k_gram_part<Q, BFV>), grid, dim3(64), 0, st, n, d, X, p0, bw, ncols, rows, part)
