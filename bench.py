@@ -323,7 +323,9 @@ def main():
     bcols = ((p.block + 15) // 16) * 16
     gram_flops = 2.0 * p.num_users * p.dim * bcols  # W^T W[:, pi] for an item pass
     dense_flops = 2.0 * p.num_users * p.dim * bcols  # W G^pi for a user pass
-    pred_bytes = p.nnz * (4.0 * p.dim + 8) + 4.0 * p.num_users * p.dim
+    # the epoch-start cache relative to block 0 needs the d - b columns outside the block
+    pred_cols = p.dim - min(p.block, p.dim)
+    pred_bytes = p.nnz * (4.0 * pred_cols + 8) + 4.0 * p.num_users * pred_cols
     seg_nnz = int(li[li > SEG_LEN].sum())
     seg_bytes = seg_nnz * (4.0 * p.block + 12)
 
@@ -339,8 +341,9 @@ def main():
         "dense_W": _rate("dense_user", dense_flops, 1e12, PEAK_FP32_MFMA, "TFLOP/s",
                          "k_dense_vec: alpha0 W G^pi + lambda W_pi per user pass"),
         "predict": _rate("predict", pred_bytes, 1e9, PEAK_HBM, "GB/s",
-                         "prediction recompute, algorithmic bytes (partner row, id, output per observation; "
-                         "W once); the L2 serves repeated partner rows, so frac can exceed what HBM sees"),
+                         "prediction recompute (the cache relative to block 0: the d - b other columns), "
+                         "algorithmic bytes (partner columns, id, output per observation; W once); the L2 "
+                         "serves repeated partner rows, so frac can exceed what HBM sees"),
         "seg_item": _rate("seg_item", seg_bytes, 1e9, PEAK_HBM, "GB/s",
                           "item long-row segments, algorithmic gather bytes (partner block, id, slot, cache)"),
     }

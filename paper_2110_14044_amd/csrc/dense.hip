@@ -53,23 +53,26 @@ __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int
     }
 }
 
-// Same computation for d = 64*J with the row held in registers (the excluded or
-// included columns are masked once per row): the partner ids of 64 observations
-// are loaded at once and 4 observations' rows are in flight per 16-lane group.
-template <int J>
+// Same computation for d = 64*J with the row held in registers: only the JL chunks of 64
+// columns listed in ch take part (chunks wholly inside, or wholly outside, the summed
+// range are skipped, so the partner rows are read only where they count; within a listed
+// chunk the excluded or included columns are masked once per row).  The partner ids of 64
+// observations are loaded at once and 4 observations' rows are in flight per 16-lane group.
+template <int J, int JL>
 __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ W,
                                                       const float* __restrict__ H, int32_t p0, int32_t bw, bool inside,
-                                                      const float* __restrict__ base, float* __restrict__ out) {
+                                                      int4 ch, const float* __restrict__ base, float* __restrict__ out) {
     constexpr int D = 64 * J;
     const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     if (u >= U) return;
-    float4 w[J];
+    const int chs[4] = {ch.x, ch.y, ch.z, ch.w};
+    float4 w[JL];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        float4 v = *reinterpret_cast<const float4*>(W + (size_t)u * D + 4 * q16 + 64 * j);
-        const int f = 4 * q16 + 64 * j;
+    for (int j = 0; j < JL; ++j) {
+        const int f = 4 * q16 + 64 * chs[j];
+        float4 v = *reinterpret_cast<const float4*>(W + (size_t)u * D + f);
         v.x = ((f + 0 >= p0 && f + 0 < p0 + bw) == inside) ? v.x : 0.f;
         v.y = ((f + 1 >= p0 && f + 1 < p0 + bw) == inside) ? v.y : 0.f;
         v.z = ((f + 2 >= p0 && f + 2 < p0 + bw) == inside) ? v.z : 0.f;
@@ -83,34 +86,31 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
         const int cnt = (int)min((int64_t)64, hi - c0);
         const int nsteps = (cnt + 3) >> 2;
         for (int st = 0; st < nsteps; st += 4) {
-            float4 h[4][J];
+            // four steps' rows loaded together (steps past the chunk read a valid row, unused)
+            float4 h[4][JL];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if (st + v < nsteps) {
-                    const int i = __shfl(ci, 4 * (st + v) + g4);
+                const int i = __shfl(ci, (4 * (st + v) + g4) & 63);
 #pragma unroll
-                    for (int j = 0; j < J; ++j)
-                        h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * D + 4 * q16 + 64 * j);
-                }
+                for (int j = 0; j < JL; ++j)
+                    h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * D + 4 * q16 + 64 * chs[j]);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if (st + v < nsteps) {
-                    float s = 0.f;
+                float s = 0.f;
 #pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        s = fmaf(w[j].x, h[v][j].x, s);
-                        s = fmaf(w[j].y, h[v][j].y, s);
-                        s = fmaf(w[j].z, h[v][j].z, s);
-                        s = fmaf(w[j].w, h[v][j].w, s);
-                    }
-                    s += __shfl_xor(s, 8);
-                    s += __shfl_xor(s, 4);
-                    s += __shfl_xor(s, 2);
-                    s += __shfl_xor(s, 1);
-                    const int idx = 4 * (st + v) + g4;
-                    if (q16 == 0 && idx < cnt) out[c0 + idx] = inside ? base[c0 + idx] + s : s;
+                for (int j = 0; j < JL; ++j) {
+                    s = fmaf(w[j].x, h[v][j].x, s);
+                    s = fmaf(w[j].y, h[v][j].y, s);
+                    s = fmaf(w[j].z, h[v][j].z, s);
+                    s = fmaf(w[j].w, h[v][j].w, s);
                 }
+                s += __shfl_xor(s, 8);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 1);
+                const int idx = 4 * (st + v) + g4;
+                if (q16 == 0 && idx < cnt) out[c0 + idx] = inside ? base[c0 + idx] + s : s;
             }
         }
     }
@@ -608,16 +608,31 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
     if (c->U == 0 || c->nnz == 0) return;
     const int32_t p0 = blk * c->b, bw = std::min(c->b, c->d - p0);
     const unsigned g = nblk(c->U, 4);
-    if (c->d == 64)
-        hipLaunchKernelGGL(k_predict_rows<1>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
-                           bw, inside, c->yhat, out);
-    else if (c->d == 128)
-        hipLaunchKernelGGL(k_predict_rows<2>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
-                           bw, inside, c->yhat, out);
-    else if (c->d == 256)
-        hipLaunchKernelGGL(k_predict_rows<4>, dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H, p0,
-                           bw, inside, c->yhat, out);
-    else if (c->d == 512)
+    if (c->d == 64 || c->d == 128 || c->d == 256) {
+        // the 64-column chunks that hold at least one summed column
+        int chs[4] = {0, 0, 0, 0}, nc = 0;
+        for (int j = 0; j < c->d / 64; ++j) {
+            bool any = false;
+            for (int f = 64 * j; f < 64 * j + 64; ++f) any = any || ((f >= p0 && f < p0 + bw) == inside);
+            if (any) chs[nc++] = j;
+        }
+        if (nc == 0) chs[nc++] = 0;  // nothing summed: one masked chunk keeps the output defined
+        const int4 ch = make_int4(chs[0], chs[1], chs[2], chs[3]);
+#define IALS_PRED(JV, JLV)                                                                                     \
+    hipLaunchKernelGGL((k_predict_rows<JV, JLV>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, \
+                       c->H, p0, bw, inside, ch, c->yhat, out)
+        if (c->d == 64) IALS_PRED(1, 1);
+        else if (c->d == 128) {
+            if (nc == 1) IALS_PRED(2, 1);
+            else IALS_PRED(2, 2);
+        } else {
+            if (nc == 1) IALS_PRED(4, 1);
+            else if (nc == 2) IALS_PRED(4, 2);
+            else if (nc == 3) IALS_PRED(4, 3);
+            else IALS_PRED(4, 4);
+        }
+#undef IALS_PRED
+    } else if (c->d == 512)
         hipLaunchKernelGGL((k_predict_wide<2, 4>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
                            p0, bw, inside, c->yhat, out);
     else if (c->d == 1024)
