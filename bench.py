@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "epoch sec + nnz·b/s; p99 fold-in ms vs plain FP32 iALS++ at matched loss"
-SEG_LEN = 1024          # rows longer than this are accumulated by the segment kernel
+SEG_LEN = 512           # the library's default segment length (rows longer are accumulated in segments)
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0       # GB/s
 SERVE_RATES = (1000, 5000, 20000)  # open-loop Poisson arrival rates, requests per second
@@ -38,15 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def rows_work(lengths, b, trans_fraction):
-    """Algorithmic FLOPs and bytes of one row-kernel launch.  Rows of <= SEG_LEN observations are
-    accumulated there (per observation: rank-1 Hessian update 2 b^2, gradient 2 b, prediction
-    dot product 2 b, plus 2 b more when the pass moves the cache to a new block); every row is
-    solved (LDL^T factorisation b^3/3 + two triangular solves 2 b^2) and updated.  trans_fraction is the
+def rows_work(lengths, b, trans_fraction, seg_len=SEG_LEN):
+    """Algorithmic FLOPs and bytes of one row-kernel launch.  Rows of <= seg_len observations are
+    accumulated there (per observation: rank-1 Hessian update 2 b^2, gradient 2 b, prediction dot
+    product 2 b, plus 2 b more when the pass moves the cache to a new block); every row is solved
+    (LDL^T factorisation b^3/3 + two triangular solves 2 b^2) and updated.  trans_fraction is the
     share of launches that move the cache."""
     import numpy as np
     lengths = np.asarray(lengths, np.int64)
-    nnz_s = int(lengths[lengths <= SEG_LEN].sum())
+    nnz_s = int(lengths[lengths <= seg_len].sum())
     n = lengths.size
     per_obs_flops = 2.0 * b * b + 4.0 * b + trans_fraction * 2.0 * b
     flops = per_obs_flops * nnz_s + n * (b ** 3 / 3.0 + 2.0 * b * b)
@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch epochs kernel by kernel")
     ap.add_argument("--block", type=int, default=0, help="block size b (0: the workload's)")
     ap.add_argument("--seg-len", type=int, default=0,
-                    help="observations per segment of long rows (0: the library default, 1024)")
+                    help="observations per segment of long rows (0: the library default, 512)")
     ap.add_argument("--deal", choices=("auto", "static", "queue"), default="auto", help="row dealing of the row kernels")
     ap.add_argument("--autotune", action="store_true",
                     help="choose b, row dealing and segment length by measurement first (cached in --tune-cache)")
@@ -298,7 +298,8 @@ def main():
     # dominant kernel: the row-kernel family with the most time per epoch
     dom = max(("rows_user", "rows_user_move", "rows_item"),
               key=lambda k: kern.get(k, {"ms_per_epoch": 0})["ms_per_epoch"])
-    flops, bytes_ = rows_work(li if dom == "rows_item" else lu, p.block, 1.0 if dom.endswith("_move") else 0.0)
+    flops, bytes_ = rows_work(li if dom == "rows_item" else lu, p.block, 1.0 if dom.endswith("_move") else 0.0,
+                              seg_len or SEG_LEN)
     avg_s = kern[dom]["avg_ms"] / 1e3
     achieved = flops / avg_s / 1e12
     if p.block > 64:
@@ -326,7 +327,7 @@ def main():
     # the epoch-start cache relative to block 0 needs the d - b columns outside the block
     pred_cols = p.dim - min(p.block, p.dim)
     pred_bytes = p.nnz * (4.0 * pred_cols + 8) + 4.0 * p.num_users * pred_cols
-    seg_nnz = int(li[li > SEG_LEN].sum())
+    seg_nnz = int(li[li > (seg_len or SEG_LEN)].sum())
     seg_bytes = seg_nnz * (4.0 * p.block + 12)
 
     def _rate(name, work, scale, peak, unit, what):
@@ -397,7 +398,7 @@ def main():
         "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16" else "f32", "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.num_users} users x {wl.num_items} items, {wl.nnz} observations "
                                f"(y=alpha=1), d={wl.dim}, b={p.block}, alpha0={wl.alpha0}, lambda={wl.lam}",
-                   "epoch_s": epoch_s, "parallelism": "single GPU", "deal": deal, "seg_len": seg_len or 1024},
+                   "epoch_s": epoch_s, "parallelism": "single GPU", "deal": deal, "seg_len": seg_len or SEG_LEN},
         "autotune": tuned,
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
         "roofline": roofline, "kernel_rates": kernel_rates, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,

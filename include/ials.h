@@ -89,7 +89,7 @@ typedef struct {
     uint32_t flags;             /* IALS_FLAG_* bits */
     uint32_t seg_len;           /* rows longer than this are accumulated in segments of this many
                                    observations (split-K); a multiple of 64 in [256, 65536];
-                                   0 selects 1024 */
+                                   0 selects 512 */
     uint64_t hbm_budget;        /* upper bound on library-owned device bytes; 0 = no bound */
 } ials_config;
 

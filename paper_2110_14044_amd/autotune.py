@@ -29,7 +29,8 @@ import os
 from . import binding
 
 CANDIDATE_B = (32, 64, 128, 256)
-SEG_LENS = (512, 1024, 2048)
+SEG_LENS = (256, 512, 1024, 2048)
+DEFAULT_SEG_LEN = 512  # the library's segment length when ials_config.seg_len is 0
 DEALS = ("static", "queue")
 
 
@@ -95,7 +96,7 @@ def estimate_epoch_ms(problem, block: int, precision: int = binding.IALS_PREC_FP
                    "user_move_ms": move_user, "item_ms": item}
             if best is None or cur["epoch_ms"] < best["epoch_ms"]:
                 best = cur
-        best.update({"block": block, "nblocks": nb, "deal": deal, "seg_len": seg_len or 1024})
+        best.update({"block": block, "nblocks": nb, "deal": deal, "seg_len": seg_len or DEFAULT_SEG_LEN})
         return best
     finally:
         tr.close()
@@ -133,7 +134,7 @@ def tune(problem, precision: int = binding.IALS_PREC_FP32, candidates=CANDIDATE_
         if r["epoch_ms"] < best["epoch_ms"]:
             best = r
     for seg in SEG_LENS:
-        if seg == 1024:
+        if seg == DEFAULT_SEG_LEN:
             continue
         r = estimate_epoch_ms(problem, best["block"], precision, deal=best["deal"], seg_len=seg)
         trials.append(r)

@@ -15,10 +15,10 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
-// Rows longer than the context's segment length (1024 by default) are split into
+// Rows longer than the context's segment length (512 by default) are split into
 // segments of that many observations, each accumulated by its own wavefront (or
 // workgroup), then reduced in a fixed order.
-constexpr int kSegLenDefault = 1024;
+constexpr int kSegLenDefault = 512;
 
 // Device-side counters/flags block (int64), zeroed at create.
 enum Counter : int {
