@@ -608,7 +608,12 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
     if (c->U == 0 || c->nnz == 0) return;
     const int32_t p0 = blk * c->b, bw = std::min(c->b, c->d - p0);
     const unsigned g = nblk(c->U, 4);
-    if (c->d == 64 || c->d == 128 || c->d == 256) {
+    // the specialised kernels read rows with 16-byte loads
+    const bool aligned = reinterpret_cast<uintptr_t>(c->W) % 16 == 0 && reinterpret_cast<uintptr_t>(c->H) % 16 == 0;
+    if (!aligned) {
+        hipLaunchKernelGGL(k_predict, dim3(g), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col, c->W, c->H, p0, bw,
+                           inside, c->yhat, out);
+    } else if (c->d == 64 || c->d == 128 || c->d == 256) {
         // the 64-column chunks that hold at least one summed column
         int chs[4] = {0, 0, 0, 0}, nc = 0;
         for (int j = 0; j < c->d / 64; ++j) {
@@ -656,7 +661,8 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
-    if (!bf16 && d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0) {
+    if (!bf16 && d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0 &&
+        reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         // full 64 x 64 tiles with 16-byte loads; four wavefronts per block, so a quarter of the
         // blocks (and of the partials the reduction reads) for the same number of wavefronts
         const int rv = chunk_rows_for(n, ft * qg, 512, 256);
@@ -696,7 +702,7 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
     if (n == 0) return;
     const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
     const int B = c->B;
-    if (B % 64 == 0 && c->d % 16 == 0) {
+    if (B % 64 == 0 && c->d % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         hipLaunchKernelGGL(k_dense_vec, dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X, c->G, p0,
                            bw, c->alpha0, c->lambda, c->R0);
         return;
