@@ -13,14 +13,15 @@
 // per-segment partials instead (k_seg_big), summed in segment order.
 //
 // Factorisation: the tiles go to LDS (packed lower tiles, 256 floats each) and a
-// blocked right-looking LDL^T runs over them, panel by panel: wave 0 takes the 16
-// columns of panel K with a lane per row (lane l holds rows l, 64 + l, ...), eliminates
-// them step by step with the forward substitution folded in (column k of the diagonal
-// tile is copied to every row group and read with a DPP row broadcast, so each update
-// is one fused multiply-add) and writes back -L with the pivots; after a barrier every
-// wave subtracts L_IK diag(piv) L_JK^T from its own tiles (I, J), K < J <= I, on the
-// matrix cores.  Wave 0 then solves L^T x = D^-1 z column by column from the last.  A
-// row whose pivots fail the ratio test is redone in float64 by k_fallback_big.
+// blocked right-looking LDL^T runs over them, panel by panel.  The 16 columns of panel K
+// go to a lane per row: every wave holds the panel's diagonal tile in lanes 0-15 and its
+// share of the rows below in the other lanes, and eliminates them step by step with the
+// forward substitution folded in (column k of the diagonal tile is copied to every 16-lane
+// row and read with a DPP row broadcast, so each update is one fused multiply-add); the
+// panel goes back as -L with the pivots, and after a barrier every wave subtracts
+// L_IK diag(piv) L_JK^T from its own tiles (I, J), K < J <= I, on the matrix cores.  Wave 0
+// then solves L^T x = D^-1 z column by column from the last.  A row whose pivots fail the
+// ratio test is redone in float64 by k_fallback_big.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -296,77 +297,68 @@ __device__ inline floatx4 mm_pdqt(floatx4 c, const float* P, const float* Q, con
     return c;
 }
 
-// Step KK..15 of panel K for NH = B / 64 rows per lane (row 64 h + lane in p[h]); see
-// big_panel.  src: ds_bpermute address of this lane's position in row group K & 3.
-template <int NH, int KK>
-__device__ inline void big_steps(float (*p)[16], float* g, float* pvl, const float* lk, int K, int src, int lane) {
+// Steps KK..15 of a panel with one row per lane: lanes 0-15 hold the panel's diagonal tile,
+// the other lanes rows below it (see big_panel); lk = this lane's row - 16K (< 0: no row).
+template <int KK>
+__device__ inline void big_steps(float* p, float& g, float* pvl, float lk, int K, int src, bool lead) {
     if constexpr (KK < 16) {
-        const int hK = K >> 2, l0 = 16 * (K & 3);
-        float v = p[0][KK], gv = g[0];
-#pragma unroll
-        for (int h = 1; h < NH; ++h) {
-            v = (hK == h) ? p[h][KK] : v;
-            gv = (hK == h) ? g[h] : gv;
-        }
-        const float piv = readlane(v, l0 + KK);
-        if (lane == 0) pvl[16 * K + KK] = piv;
+        const float piv = readlane(p[KK], KK);
+        if (lead) pvl[16 * K + KK] = piv;
         const float nr = __builtin_amdgcn_rcpf(-piv);
-        float tn[NH];
-#pragma unroll
-        for (int h = 0; h < NH; ++h) tn[h] = p[h][KK] * nr * __builtin_amdgcn_fmed3f(lk[h] - (float)KK, 0.f, 1.f);
+        const float tn = p[KK] * nr * __builtin_amdgcn_fmed3f(lk - (float)KK, 0.f, 1.f);  // -t_i
         if constexpr (KK < 15) {
-            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
-            eliminate_cols<KK + 1, true>(p[0], D, tn[0]);
-#pragma unroll
-            for (int h = 1; h < NH; ++h) eliminate_cols<KK + 1, false>(p[h], D, tn[h]);
+            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p[KK])));
+            eliminate_cols<KK + 1, true>(p, D, tn);
         }
-        const float gk = readlane(gv, l0 + KK);
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            g[h] = fmaf(tn[h], gk, g[h]);
-            p[h][KK] = tn[h];
-        }
-        big_steps<NH, KK + 1>(p, g, pvl, lk, K, src, lane);
+        g = fmaf(tn, readlane(g, KK), g);
+        p[KK] = tn;
+        big_steps<KK + 1>(p, g, pvl, lk, K, src, lead);
     }
 }
 
-// Panel K of the LDL^T factorisation (wave 0): the rows 16K .. B-1 of tile column K go to
-// a lane per row, each step k takes piv = A_kk, t_i = A_ik / piv for the rows below k,
-// g_i -= t_i g_k and A_ij -= t_i A_jk for the panel's later columns (column k of the
-// diagonal tile copied from its lanes and read with a row broadcast), and the rows are
-// written back holding -t (zeros on and above the diagonal); the pivots go to pvl.
+// Panel K of the LDL^T factorisation, shared by the NW wavefronts: every wave holds the
+// panel's 16 x 16 diagonal tile in lanes 0-15 (the same rows, eliminated identically in
+// every wave) and its share of the rows below in lanes 16-63 (NT <= 16 keeps a share within
+// 48 rows).  Each step k takes piv = A_kk, t_i = A_ik / piv for the rows below k,
+// g_i -= t_i g_k and A_ij -= t_i A_jk for the panel's later columns, column k of the
+// diagonal tile being copied to every 16-lane row and read with a row broadcast.  A wave
+// writes back its own rows (wave 0 also the diagonal tile and the pivots) holding -t, zeros
+// on and above the diagonal; gl holds the gradient, updated in place.
 template <int NT>
-__device__ inline void big_panel(float* mat, float* pvl, float* g, int lane, int K) {
-    constexpr int NH = NT / 4;
-    float p[NH][16];
-    float lk[NH];
-    bool mine[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        const int r = 64 * h + lane;
-        mine[h] = r >= 16 * K;
-        const float* src = mine[h] ? mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16 : mat;
-#pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4) {
-            const float4 v = *reinterpret_cast<const float4*>(src + 4 * c4);
-            p[h][4 * c4 + 0] = v.x;
-            p[h][4 * c4 + 1] = v.y;
-            p[h][4 * c4 + 2] = v.z;
-            p[h][4 * c4 + 3] = v.w;
-        }
-        lk[h] = (float)(r - 16 * K);
+__device__ inline void big_panel(float* mat, float* pvl, float* gl, int lane, int wave, int K) {
+    constexpr int B = 16 * NT, NW = NT / 2;
+    const int below = B - 16 * K - 16;           // rows under the diagonal tile
+    const int share = (below + NW - 1) / NW;    // rows per wave
+    int r;
+    if (lane < 16) {
+        r = 16 * K + lane;
+    } else {
+        const int j = lane - 16;
+        r = (j < share) ? 16 * K + 16 + wave * share + j : B;
+        if (r >= B) r = -1;
     }
-    big_steps<NH, 0>(p, g, pvl, lk, K, (16 * (K & 3) + (lane & 15)) * 4, lane);
+    const bool has = r >= 0;
+    const float* src = has ? mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16 : mat;
+    float p[16];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        const int r = 64 * h + lane;
-        if (mine[h]) {
-            float* dst = mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16;
+    for (int c4 = 0; c4 < 4; ++c4) {
+        const float4 v = *reinterpret_cast<const float4*>(src + 4 * c4);
+        p[4 * c4 + 0] = v.x;
+        p[4 * c4 + 1] = v.y;
+        p[4 * c4 + 2] = v.z;
+        p[4 * c4 + 3] = v.w;
+    }
+    float g = has ? gl[r] : 0.f;
+    const float lk = has ? (float)(r - 16 * K) : -1.f;
+    __syncthreads();  // every wave has read the diagonal tile before wave 0 writes it back
+    big_steps<0>(p, g, pvl, lk, K, (lane & 15) * 4, wave == 0 && lane == 0);
+    // rows below the tile: their wave; the diagonal tile: wave 0 (every wave holds it)
+    if (has && (lane >= 16 || wave == 0)) {
+        float* dst = mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16;
 #pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4)
-                *reinterpret_cast<float4*>(dst + 4 * c4) =
-                    make_float4(p[h][4 * c4], p[h][4 * c4 + 1], p[h][4 * c4 + 2], p[h][4 * c4 + 3]);
-        }
+        for (int c4 = 0; c4 < 4; ++c4)
+            *reinterpret_cast<float4*>(dst + 4 * c4) = make_float4(p[4 * c4], p[4 * c4 + 1], p[4 * c4 + 2], p[4 * c4 + 3]);
+        gl[r] = g;
     }
 }
 
@@ -460,14 +452,9 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
         // every wave then applies the panel to its own tiles on the matrix cores.
         float* zero = lds_big + L::YP;  // 16 x 16 zeros (back substitution)
         float* pvl = zero + 256;        // [B] pivots
-        float g[NH];
-        if (I1 == 0) {
-#pragma unroll
-            for (int h = 0; h < NH; ++h) g[h] = gl[64 * h + lane];
-        }
 #pragma unroll 1
         for (int K = 0; K < NT; ++K) {
-            if (I1 == 0) big_panel<NT>(mat, pvl, g, lane, K);
+            big_panel<NT>(mat, pvl, gl, lane, I1, K);
             __syncthreads();
             // trailing tiles: A_IJ -= L_IK diag(piv) L_JK^T for K < J <= I (the panel holds -L)
 #pragma unroll 1
@@ -485,11 +472,6 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
             }
             __syncthreads();
         }
-        if (I1 == 0) {
-#pragma unroll
-            for (int h = 0; h < NH; ++h) gl[64 * h + lane] = g[h];
-        }
-        __syncthreads();
         // pivot check over the real coordinates (every wave, from LDS)
         float pmin = 3.0e38f, pmax = 0.f;
 #pragma unroll
