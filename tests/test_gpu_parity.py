@@ -71,7 +71,8 @@ def test_predictions_and_gramians_at_width(d, b):
 
 def test_unaligned_tables():
     """W and H borrowed at a 4-byte offset: the kernels that read rows with 16-byte loads
-    are replaced by their scalar forms, with the same results."""
+    are replaced by their scalar forms, with the same results (checked step by step:
+    predictions, Gramians, one user pass, one epoch)."""
     import torch
     from paper_2110_14044_amd import binding
     p = synth.small_problem(97, 500, 300, 8000, 128, 64, labels=True, std=0.1)
@@ -86,15 +87,44 @@ def test_unaligned_tables():
     u = np.ascontiguousarray(p.user, np.int32)
     i = np.ascontiguousarray(p.item, np.int32)
     y = np.ascontiguousarray(p.y, np.float32)
-    coo = binding.make_coo(u, i, y, None, binding.IALS_MEM_HOST)
+    a = np.ascontiguousarray(p.alpha, np.float32)
+    coo = binding.make_coo(u, i, y, a, binding.IALS_MEM_HOST)
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    csr, ys, as_ = oracle_setup(p)
+    ctx = binding.ials_create(cfg, coo, W, H, stream)
+    try:
+        W64, H64 = p.W0.astype(np.float64), p.H0.astype(np.float64)
+        yhat = oracle.predict(csr, W64, H64)
+        e = rel(binding.ials_get_predictions(ctx, p.nnz), yhat)
+        say(f"unaligned: predictions {e:.1e}")
+        assert e < 1e-6
+        for which, X in ((0, W64), (1, H64)):
+            G = torch.empty((p.dim, p.block), device="cuda")
+            binding.ials_gramian(ctx, which, 0, G)
+            torch.cuda.synchronize()
+            e = rel(host(G), oracle.gramian(X, 0, p.block))
+            say(f"unaligned: Gramian {which} {e:.1e}")
+            assert e < 1e-5
+        binding.ials_block_sweep(ctx, 0, 0)
+        torch.cuda.synchronize()
+        Wo, Ho = W64.copy(), H64.copy()
+        oracle.block_pass(csr, "user", 0, p.block, p.alpha0, p.lam, Wo, Ho, yhat, oracle.gramian(H64, 0, p.block),
+                          ys, as_)
+        e = rel(host(W), Wo)
+        say(f"unaligned: user pass {e:.1e}")
+        assert e < 1e-5
+    finally:
+        binding.ials_destroy(ctx)
+    # one epoch from the start on a fresh context
+    W.copy_(torch.from_numpy(p.W0))
+    H.copy_(torch.from_numpy(p.H0))
     torch.cuda.synchronize()
     ctx = binding.ials_create(cfg, coo, W, H, stream)
     try:
         binding.ials_epoch(ctx, 1)
         L, _ = binding.ials_loss(ctx)
         torch.cuda.synchronize()
-        csr, ys, as_ = oracle_setup(p)
         Wr, Hr, _, losses = oracle.epochs(csr, p.W0, p.H0, p.block, p.alpha0, p.lam, 1, ys, as_)
         ew, eh = rel(host(W), Wr), rel(host(H), Hr)
         el = abs(L - losses[-1]) / abs(losses[-1])
@@ -159,7 +189,8 @@ def test_labels_weights_and_empty_rows():
     _epoch_check(p, 2, 1e-4, 1e-6)
 
 
-@pytest.mark.parametrize("d,b", [(20, 8), (48, 48), (64, 64), (16, 1), (40, 16), (128, 64)])
+@pytest.mark.parametrize("d,b", [(20, 8), (48, 48), (64, 64), (16, 1), (40, 16), (128, 64), (112, 64), (100, 64),
+                                 (96, 32)])
 def test_block_shapes(d, b):
     p = synth.small_problem(40 + d + b, 500, 300, 6000, d, b, labels=False, std=0.1)
     _epoch_check(p, 1, 1e-4, 1e-6)
