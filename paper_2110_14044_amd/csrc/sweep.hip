@@ -319,8 +319,11 @@ __global__ __launch_bounds__(256) void k_seg_group(SweepArgs A, int32_t stride) 
 }
 
 // Blocked factorisation storage: panel K (16 columns, rows 16K..B-1) of the factor L is
-// kept in LDS with row stride kPS; panels are packed one after another.
-constexpr int kPS = 16;
+// kept in LDS with row stride kPS; panels are packed one after another.  A stride of 20
+// floats keeps rows 16-byte aligned and spreads the accesses over the banks: the
+// accumulator-layout stores (rows 4 apart in a half-wave), the lane-per-row 16-byte loads
+// (8 rows per cycle) and the operand loads of the trailing updates.
+constexpr int kPS = 20;
 template <int NT>
 constexpr int panel_rows() { return 16 * NT * (NT + 1) / 2; }
 template <int NT>
