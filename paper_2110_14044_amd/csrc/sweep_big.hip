@@ -12,8 +12,8 @@
 // gradient and moves the cache.  Rows longer than the segment length take
 // per-segment partials instead (k_seg_big), summed in segment order.
 //
-// Factorisation: the tiles go to LDS (packed lower tiles, 256 floats each) and a
-// blocked right-looking LDL^T runs over them, panel by panel.  The 16 columns of panel K
+// Factorisation: the tiles go to LDS (packed lower tiles, 16 rows at a pitch of 20 floats,
+// or 16 when B = 256) and a blocked right-looking LDL^T runs over them, panel by panel.  The 16 columns of panel K
 // go to a lane per row: every wave holds the panel's diagonal tile in lanes 0-15 and its
 // share of the rows below in the other lanes, and eliminates them step by step with the
 // forward substitution folded in (column k of the diagonal tile is copied to every 16-lane
@@ -60,9 +60,12 @@ __device__ inline int tile_id(int I, int J) { return I * (I + 1) / 2 + J; }
 template <int NT>
 struct BigLds {
     static constexpr int B = 16 * NT, NW = NT / 2, NTL = NT * (NT + 1) / 2;
-    static constexpr int MAT = 0;                 // NTL packed lower tiles, row-major 16 x 16
-    static constexpr int YP = MAT + NTL * 256;    // [NW][256] each wave's copy of Y_KK
-    static constexpr int XW = YP + NW * 256;      // [NW][B]   each wave's copy of the solution
+    // row pitch of a tile in LDS: 20 floats spread the accesses over the banks (rows stay
+    // 16-byte aligned); B = 256 keeps 16 for its LDS budget
+    static constexpr int TP = NT <= 8 ? 20 : 16, TSZ = 16 * TP;
+    static constexpr int MAT = 0;                 // NTL packed lower tiles, row-major 16 x 16 at pitch TP
+    static constexpr int YP = MAT + NTL * TSZ;    // [TSZ] a zero tile, then [B] the pivots
+    static constexpr int XW = YP + TSZ + B;       // [NW][B]   each wave's copy of the solution
     static constexpr int G = XW + NW * B;         // [B]       gradient, then z = L^-1 g
     static constexpr int SP = G + B;              // [2][NW][16] back-substitution partials
     static constexpr int OWN = SP + 2 * NW * 16;  // [2][B] the row's own values (pass block, cache block)
@@ -266,32 +269,25 @@ __global__ __launch_bounds__(NT * 32) void k_seg_big(SweepArgs A) {
     }
 }
 
-// tile (accumulator layout: lane l, register j = element (4(l/16)+j, l%16)) <-> LDS row-major
+// tile (accumulator layout: lane l, register j = element (4(l/16)+j, l%16)) <-> LDS row-major, pitch TP
+template <int TP>
 __device__ inline void tile_store(float* T, floatx4 c, int lane) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) T[(4 * (lane >> 4) + j) * 16 + (lane & 15)] = c[j];
+    for (int j = 0; j < 4; ++j) T[(4 * (lane >> 4) + j) * TP + (lane & 15)] = c[j];
 }
+template <int TP>
 __device__ inline floatx4 tile_load(const float* T, int lane) {
     floatx4 c;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) c[j] = T[(4 * (lane >> 4) + j) * 16 + (lane & 15)];
+    for (int j = 0; j < 4; ++j) c[j] = T[(4 * (lane >> 4) + j) * TP + (lane & 15)];
     return c;
 }
-// c += sgn * P Q^T for 16 x 16 row-major tiles P, Q
-__device__ inline floatx4 mm_pqt(floatx4 c, const float* P, const float* Q, float sgn, int lane) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int o = (lane & 15) * 16 + 4 * s + (lane >> 4);
-        c = mfma4(sgn * P[o], Q[o], c);
-    }
-    return c;
-}
-
-// c -= (P diag(pv)) Q^T for 16 x 16 row-major tiles P, Q (pv: the 16 pivots of P's columns)
+// c -= (P diag(pv)) Q^T for 16 x 16 row-major tiles P, Q at pitch TP (pv: the 16 pivots of P's columns)
+template <int TP>
 __device__ inline floatx4 mm_pdqt(floatx4 c, const float* P, const float* Q, const float* pv, int lane) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int o = (lane & 15) * 16 + 4 * s + (lane >> 4);
+        const int o = (lane & 15) * TP + 4 * s + (lane >> 4);
         c = mfma4(-P[o] * pv[4 * s + (lane >> 4)], Q[o], c);
     }
     return c;
@@ -338,7 +334,8 @@ __device__ inline void big_panel(float* mat, float* pvl, float* gl, int lane, in
         if (r >= B) r = -1;
     }
     const bool has = r >= 0;
-    const float* src = has ? mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16 : mat;
+    constexpr int TP = BigLds<NT>::TP, TSZ = BigLds<NT>::TSZ;
+    const float* src = has ? mat + tile_id(r >> 4, K) * TSZ + (r & 15) * TP : mat;
     float p[16];
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
@@ -354,7 +351,7 @@ __device__ inline void big_panel(float* mat, float* pvl, float* gl, int lane, in
     big_steps<0>(p, g, pvl, lk, K, (lane & 15) * 4, wave == 0 && lane == 0);
     // rows below the tile: their wave; the diagonal tile: wave 0 (every wave holds it)
     if (has && (lane >= 16 || wave == 0)) {
-        float* dst = mat + tile_id(r >> 4, K) * 256 + (r & 15) * 16;
+        float* dst = mat + tile_id(r >> 4, K) * TSZ + (r & 15) * TP;
 #pragma unroll
         for (int c4 = 0; c4 < 4; ++c4)
             *reinterpret_cast<float4*>(dst + 4 * c4) = make_float4(p[4 * c4], p[4 * c4 + 1], p[4 * c4 + 2], p[4 * c4 + 3]);
@@ -369,10 +366,11 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
     extern __shared__ __align__(16) float lds_big[];
     const int lane0 = threadIdx.x & 63;
     const int wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    static_assert(BigLds<NT>::NW * NT * 128 <= BigLds<NT>::NTL * 256, "staging fits in the matrix region");
+    static_assert(BigLds<NT>::NW * NT * 128 <= BigLds<NT>::NTL * BigLds<NT>::TSZ, "staging fits in the matrix region");
+    constexpr int TP = L::TP, TSZ = L::TSZ;
     float* mat = lds_big + L::MAT;
     float* gl = lds_big + L::G;
-    for (int e = threadIdx.x; e < 256; e += blockDim.x) lds_big[L::YP + e] = 0.f;
+    for (int e = threadIdx.x; e < TSZ; e += blockDim.x) lds_big[L::YP + e] = 0.f;
     __syncthreads();
 
     for (int it = blockIdx.x; it < A.nrows; it += gridDim.x) {
@@ -443,15 +441,15 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
         for (int m = 0; m <= NT; ++m) {
             int I, J;
             tile_of(m, I1, NT, I, J);
-            tile_store(mat + tile_id(I, J) * 256, acc[m], lane);
+            tile_store<TP>(mat + tile_id(I, J) * TSZ, acc[m], lane);
         }
         __syncthreads();
 
         // Blocked LDL^T on the tiles in LDS with the forward substitution folded in.  Wave 0
         // factors each 16-column panel with a lane per row (lane l holds rows l, 64 + l, ...);
         // every wave then applies the panel to its own tiles on the matrix cores.
-        float* zero = lds_big + L::YP;  // 16 x 16 zeros (back substitution)
-        float* pvl = zero + 256;        // [B] pivots
+        float* zero = lds_big + L::YP;  // 16 x 16 zeros at pitch TP (back substitution)
+        float* pvl = zero + TSZ;        // [B] pivots
 #pragma unroll 1
         for (int K = 0; K < NT; ++K) {
             big_panel<NT>(mat, pvl, gl, lane, I1, K);
@@ -461,13 +459,13 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
             for (int pass = 0; pass < 2; ++pass) {
                 const int I = pass == 0 ? I1 : I2;
                 if (I <= K) continue;
-                const float* LI = mat + tile_id(I, K) * 256;
+                const float* LI = mat + tile_id(I, K) * TSZ;
 #pragma unroll 1
                 for (int J = K + 1; J <= I; ++J) {
-                    float* T = mat + tile_id(I, J) * 256;
-                    floatx4 c = tile_load(T, lane);
-                    c = mm_pdqt(c, LI, mat + tile_id(J, K) * 256, pvl + 16 * K, lane);
-                    tile_store(T, c, lane);
+                    float* T = mat + tile_id(I, J) * TSZ;
+                    floatx4 c = tile_load<TP>(T, lane);
+                    c = mm_pdqt<TP>(c, LI, mat + tile_id(J, K) * TSZ, pvl + 16 * K, lane);
+                    tile_store<TP>(T, c, lane);
                 }
             }
             __syncthreads();
@@ -508,13 +506,13 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
 #pragma unroll
                 for (int h = 0; h < NH; ++h) {
                     const int ti = 4 * h + (lane >> 4);  // tile column of this lane's row
-                    rowp[h] = (ti <= K) ? mat + tile_id(K, ti) * 256 + (lane & 15) : zero + (lane & 15);
+                    rowp[h] = (ti <= K) ? mat + tile_id(K, ti) * TSZ + (lane & 15) : zero + (lane & 15);
                 }
                 float lt[NH][16];
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
 #pragma unroll
-                    for (int jj = 0; jj < 16; ++jj) lt[h][jj] = rowp[h][jj * 16];
+                    for (int jj = 0; jj < 16; ++jj) lt[h][jj] = rowp[h][jj * TP];
                 const int hk = K >> 2;
                 float wk = w[0];
 #pragma unroll
