@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int
 // columns listed in ch take part (chunks wholly inside, or wholly outside, the summed
 // range are skipped, so the partner rows are read only where they count; within a listed
 // chunk the excluded or included columns are masked once per row).  The partner ids of 64
-// observations are loaded at once and 4 observations' rows are in flight per 16-lane group.
+// observations are loaded at once and 8 observations' rows are in flight per 16-lane group.
 template <int J, int JL>
 __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ W,
@@ -85,18 +85,18 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
         const int ci = (k < hi) ? col[k] : 0;
         const int cnt = (int)min((int64_t)64, hi - c0);
         const int nsteps = (cnt + 3) >> 2;
-        for (int st = 0; st < nsteps; st += 4) {
-            // four steps' rows loaded together (steps past the chunk read a valid row, unused)
-            float4 h[4][JL];
+        for (int st = 0; st < nsteps; st += 8) {
+            // eight steps' rows loaded together (steps past the chunk read a valid row, unused)
+            float4 h[8][JL];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 8; ++v) {
                 const int i = __shfl(ci, (4 * (st + v) + g4) & 63);
 #pragma unroll
                 for (int j = 0; j < JL; ++j)
                     h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * D + 4 * q16 + 64 * chs[j]);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 8; ++v) {
                 float s = 0.f;
 #pragma unroll
                 for (int j = 0; j < JL; ++j) {
