@@ -187,6 +187,37 @@ def matched_loss(p, epochs):
     return res
 
 
+def block_sweep(p, blocks, epochs):
+    """Epoch time and training loss against the block size b on one workload, every b from the
+    same W0, H0 (sec. 5.2.1: b = 1 is iCD, b = d is iALS, the cost per epoch is U-shaped in b
+    and the quality barely depends on it).  Per b: one warm-up epoch (which also captures the
+    epoch graph), then `epochs` epochs replayed from the graph and timed together; the loss is
+    evaluated after the last of them, outside the timed region."""
+    import copy
+    import torch
+    from paper_2110_14044_amd import Trainer
+    rows = []
+    for b in blocks:
+        q = copy.copy(p)
+        q.block = b
+        tr = Trainer(q, graph=True)
+        tr.epoch(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr.epoch(epochs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / epochs
+        L = tr.loss()[0]
+        tr.close()
+        rows.append({"block": b, "epoch_ms": dt * 1e3, "nnz_b_per_s": 2.0 * p.nnz * p.dim / dt,
+                     "loss_after": L, "epochs_trained": epochs + 1})
+        log(f"[bench] b={b}: {dt * 1e3:.2f} ms per epoch, loss after {epochs + 1} epochs {L:.6e}")
+    ref = rows[-1]["loss_after"]
+    for r in rows:
+        r["loss_rel_to_last"] = r["loss_after"] / ref - 1.0
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +241,9 @@ def main():
                     help="fold-in serving measurement beside the training epochs")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=2000)
+    ap.add_argument("--block-sweep", default="",
+                    help="comma-separated block sizes: report epoch time and loss per b on --workload, then exit")
+    ap.add_argument("--sweep-epochs", type=int, default=4, help="timed epochs per block size of --block-sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -239,6 +273,14 @@ def main():
         return
 
     wl = synth.workload(args.workload)
+    if args.block_sweep:
+        blocks = [int(x) for x in args.block_sweep.split(",")]
+        torch.cuda.set_device(0)
+        p = synth.make_problem(args.workload)
+        rows = block_sweep(p, blocks, args.sweep_epochs)
+        print(json.dumps({"block_sweep": rows, "workload": wl.name, "d": wl.dim, "dtype": "f32",
+                          "data": "synthetic"}))
+        return
     log(f"[bench] generating {wl.name}: {wl.num_users}x{wl.num_items}, {wl.nnz} obs, d={wl.dim} b={wl.block}")
     t0 = time.time()
     p = synth.make_problem(args.workload)
