@@ -267,3 +267,54 @@ def poisson_arrivals(seed: int, n: int, rate_per_s: float) -> np.ndarray:
     """Open-loop arrival times (seconds) of a Poisson process."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
+
+
+@dataclasses.dataclass
+class HoldoutSplit:
+    """Users held out of training: their observations are split into a fold-in part (given at
+    evaluation time, excluded from their recommendations) and a held-out part (the items the
+    ranking metrics look for).  Lists are CSR over the held-out users, item ids ascending."""
+    train: Problem
+    users: np.ndarray        # int32[n] ids of the held-out users (in the original numbering)
+    fold_ptr: np.ndarray     # int64[n+1]
+    fold_idx: np.ndarray     # int32
+    hold_ptr: np.ndarray     # int64[n+1]
+    hold_idx: np.ndarray     # int32
+
+
+def holdout_split(p: Problem, n_users: int, frac: float = 0.2, seed: int = 20211101,
+                  min_len: int = 5) -> HoldoutSplit:
+    """The shape of the holdout protocol of sec. 5.1 on a synthetic matrix: n_users users with at
+    least min_len observations are drawn at random; each keeps a random 1 - frac of its items
+    for fold-in and frac (at least one) are held out; the training problem keeps every other
+    user's observations (the held-out users' rows are empty there)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lens = np.bincount(p.user, minlength=p.num_users)
+    cand = np.nonzero(lens >= min_len)[0]
+    users = np.sort(rng.choice(cand, size=min(n_users, cand.size), replace=False)).astype(np.int32)
+    is_held = np.zeros(p.num_users, bool)
+    is_held[users] = True
+    keep = ~is_held[p.user]
+    train = dataclasses.replace(
+        p, user=p.user[keep], item=p.item[keep],
+        y=None if p.y is None else p.y[keep], alpha=None if p.alpha is None else p.alpha[keep],
+        name=p.name + "_train")
+    order = np.argsort(p.user, kind="stable")
+    ptr = np.zeros(p.num_users + 1, np.int64)
+    ptr[1:] = np.cumsum(lens)
+    fold, hold = [], []
+    for u in users:
+        its = p.item[order[ptr[u]:ptr[u + 1]]]
+        its = its[rng.permutation(its.size)]
+        nh = max(1, int(round(frac * its.size)))
+        hold.append(np.sort(its[:nh]))
+        fold.append(np.sort(its[nh:]))
+
+    def csr(lists):
+        q = np.zeros(len(lists) + 1, np.int64)
+        q[1:] = np.cumsum([x.size for x in lists])
+        return q, (np.concatenate(lists) if lists else np.zeros(0)).astype(np.int32)
+
+    fp, fi = csr(fold)
+    hp, hi = csr(hold)
+    return HoldoutSplit(train, users, fp, fi, hp, hi)

@@ -43,3 +43,18 @@ def test_serving_requests_shape():
         assert np.unique(seg).size == seg.size
     t = synth.poisson_arrivals(4, 1000, 500.0)
     assert np.all(np.diff(t) > 0) and 1.5 < t[-1] < 2.5
+
+
+def test_holdout_split_partitions_the_held_out_users():
+    p = synth.small_problem(3, 500, 300, 8000, 16, 8)
+    s = synth.holdout_split(p, 50)
+    assert s.users.size == 50 and np.all(np.diff(s.users) > 0)
+    assert s.train.nnz + s.fold_ptr[-1] + s.hold_ptr[-1] == p.nnz
+    assert not np.isin(s.train.user, s.users).any()
+    for j, u in enumerate(s.users):
+        own = np.sort(p.item[p.user == u])
+        f = s.fold_idx[s.fold_ptr[j]:s.fold_ptr[j + 1]]
+        h = s.hold_idx[s.hold_ptr[j]:s.hold_ptr[j + 1]]
+        assert h.size >= 1 and np.all(np.diff(f) > 0) and np.all(np.diff(h) > 0)
+        assert np.array_equal(np.sort(np.concatenate([f, h])), own)
+        assert h.size == max(1, round(0.2 * own.size))
