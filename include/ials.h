@@ -328,6 +328,51 @@ IALS_API ials_status ials_server_destroy(ials_server* srv);
 /* Text of the last error of srv (or of the last failed ials_server_create when srv is NULL). */
 IALS_API const char* ials_server_last_error(const ials_server* srv);
 
+/*
+ * Top-k recommendation (sec. 2: items are ranked for a user by yhat(u, i) = <w_u, h_i>, eq. 1;
+ * sec. 5.1 ranks, for each evaluated user, all items not given for that user).  For every user
+ * u < n_users, out_ids[u*k .. u*k+k) receives the k items of largest score among those not
+ * excluded for u, ordered by score descending and equal scores by id ascending, and
+ * out_scores the float32 scores (the matrix-core product of W and H); when fewer than k items
+ * are eligible the tail holds id -1 and score -inf.  Scores that are NaN are not eligible.
+ *   W        DEVICE float [n_users * d] row-major, 16-byte aligned (a batch of user rows);
+ *   H        DEVICE float [n_items * d] row-major, 16-byte aligned (may be NULL when n_items
+ *            is 0);  d a multiple of 4;
+ *   excl_ptr DEVICE int64 [n_users + 1] offsets into excl_idx, or NULL (nothing excluded);
+ *   excl_idx DEVICE int32 item ids excluded per user (ids outside [0, n_items) are ignored);
+ *   k        1 <= k <= 512;
+ *   out_ids  DEVICE int32 [n_users * k];  out_scores DEVICE float [n_users * k] or NULL;
+ *   score_buffer_bytes  bound of the score buffer (users are scored in batches whose scores
+ *            fit it; 0 selects 1 GiB); the buffer is allocated and freed on the stream;
+ *   stream   hipStream_t (NULL: the default stream).
+ * Asynchronous (returns after enqueueing); IALS_E_INVALID for bad sizes or pointers,
+ * IALS_E_NOMEM if the score buffer cannot be allocated.  Error text: ials_rank_last_error().
+ */
+IALS_API ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d,
+                                    const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, int32_t* out_ids,
+                                    float* out_scores, int64_t score_buffer_bytes, void* stream);
+
+/*
+ * Ranking metrics of the holdout evaluation (sec. 5.1 names Recall@k and NDCG@k; the
+ * definitions are those of the protocol it follows).  For ranked lists ids [n_users * k] (id -1:
+ * no item) and held-out items T_u = hold_idx[hold_ptr[u] .. hold_ptr[u+1]) (DEVICE, ids
+ * ascending within a user), metric m (kind 0: Recall, kind 1: NDCG, at k_m = ks[m] <= k) is
+ *   Recall@k_m = hits in the first k_m / min(k_m, |T_u|)
+ *   NDCG@k_m   = sum over hit ranks r <= k_m of 1/log2(r+1), over sum_{r <= min(k_m, |T_u|)} 1/log2(r+1)
+ * in float64, written to per_user [n_users * n_metrics] (DEVICE, caller-owned; NaN for a
+ * user with no held-out item).  sums_host[m] and counts_host[m] (HOST) receive the sum over
+ * users with a value and their number.  kinds and ks are HOST arrays of n_metrics <= 64.
+ * Held-out lists that are not ascending give undefined values (no invalid memory access).
+ * Synchronising.
+ */
+IALS_API ials_status ials_rank_metrics(const int32_t* ids, int64_t n_users, int32_t k, const int64_t* hold_ptr,
+                                       const int32_t* hold_idx, int32_t n_metrics, const int32_t* kinds,
+                                       const int32_t* ks, double* per_user, double* sums_host, int64_t* counts_host,
+                                       void* stream);
+
+/* Text of the last error of ials_rank_topk / ials_rank_metrics on this thread. */
+IALS_API const char* ials_rank_last_error(void);
+
 /* Library version string. */
 IALS_API const char* ials_version(void);
 

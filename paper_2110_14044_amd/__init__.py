@@ -140,3 +140,50 @@ class FoldinServer:
             self.close()
         except Exception:
             pass
+
+
+def rank_topk(W, H, k: int, excl_ptr=None, excl_idx=None, score_buffer_bytes: int = 0):
+    """Top-k items per row of W by <w_u, h_i> (eq. 1) with the excluded items (CSR per row of W,
+    ids ascending or not) removed.  W, H: float32 device tensors (d a multiple of 4);
+    excl_ptr / excl_idx: int64 / int32 host arrays or device tensors.  Returns (ids int32 [U, k],
+    scores float32 [U, k]) device tensors on the current stream."""
+    import numpy as np
+    import torch
+    dev = W.device
+    U, d = W.shape
+    I = H.shape[0]
+
+    def dev_arr(a, dt):
+        if a is None:
+            return None
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, dt))
+        return t.to(dev).contiguous()
+    ep = dev_arr(excl_ptr, np.int64)
+    ei = dev_arr(excl_idx, np.int32)
+    if ei is not None and ei.numel() == 0:
+        ei = torch.zeros(1, dtype=torch.int32, device=dev)
+    ids = torch.empty((U, k), dtype=torch.int32, device=dev)
+    sc = torch.empty((U, k), dtype=torch.float32, device=dev)
+    binding.ials_rank_topk(W.contiguous(), U, H.contiguous(), I, d, ep, ei, k, ids, sc, score_buffer_bytes,
+                           torch.cuda.current_stream())
+    return ids, sc
+
+
+def rank_metrics(ids, hold_ptr, hold_idx, metrics):
+    """Recall@k / NDCG@k of ranked lists ids (int32 device tensor [U, K]) against held-out items
+    (CSR, ids ascending per row).  metrics: sequence of ('recall' | 'ndcg', k).  Returns
+    (per_user float64 device tensor [U, m], means float64 [m], counts int64 [m])."""
+    import numpy as np
+    import torch
+    dev = ids.device
+    U, K = ids.shape
+    hp = torch.from_numpy(np.ascontiguousarray(hold_ptr, np.int64)).to(dev)
+    hi = torch.from_numpy(np.ascontiguousarray(hold_idx, np.int32)).to(dev)
+    if hi.numel() == 0:
+        hi = torch.zeros(1, dtype=torch.int32, device=dev)
+    kinds = [binding.RANK_RECALL if n == "recall" else binding.RANK_NDCG for n, _ in metrics]
+    ks = [k for _, k in metrics]
+    per = torch.empty((U, len(ks)), dtype=torch.float64, device=dev)
+    sums, counts = binding.ials_rank_metrics(ids, U, K, hp, hi, kinds, ks, per, torch.cuda.current_stream())
+    means = np.where(counts > 0, sums / np.maximum(counts, 1), np.nan)
+    return per, means, counts

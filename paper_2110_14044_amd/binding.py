@@ -115,6 +115,11 @@ _SIGS = {
     "ials_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ials_server_stats)]),
     "ials_server_destroy": (C.c_int, [C.c_void_p]),
     "ials_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "ials_rank_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "ials_rank_metrics": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ials_rank_last_error": (C.c_char_p, []),
 }
 
 
@@ -329,3 +334,39 @@ def make_config(num_users, num_items, dim, block, alpha0, lam, precision=IALS_PR
 def make_coo(user, item, y=None, alpha=None, memkind=IALS_MEM_HOST) -> ials_coo:
     n = int(user.numel() if hasattr(user, "numel") else user.size)
     return ials_coo(n, _ptr(user), _ptr(item), _ptr(y), _ptr(alpha), memkind, 0)
+
+
+RANK_RECALL = 0
+RANK_NDCG = 1
+
+
+def _check_rank(st: int):
+    if st != IALS_OK:
+        msg = load().ials_rank_last_error()
+        raise IalsError(st, msg.decode() if msg else "")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def ials_rank_topk(W, n_users: int, H, n_items: int, d: int, excl_ptr, excl_idx, k: int, out_ids, out_scores,
+                   score_buffer_bytes: int = 0, stream=None) -> None:
+    """W, H, excl_ptr, excl_idx, out_ids, out_scores: device tensors (excl_* and out_scores may be None)."""
+    _check_rank(load().ials_rank_topk(_ptr(W), n_users, _ptr(H), n_items, d, _ptr(excl_ptr), _ptr(excl_idx), k,
+                                      _ptr(out_ids), _ptr(out_scores), score_buffer_bytes, _stream(stream)))
+
+
+def ials_rank_metrics(ids, n_users: int, k: int, hold_ptr, hold_idx, kinds, ks, per_user, stream=None):
+    """ids, hold_ptr, hold_idx, per_user: device tensors; kinds / ks: sequences of ints.
+    Returns (sums float64[m], counts int64[m]) for the m metrics."""
+    kinds = np.ascontiguousarray(kinds, np.int32)
+    ks = np.ascontiguousarray(ks, np.int32)
+    sums = np.zeros(kinds.size, np.float64)
+    counts = np.zeros(kinds.size, np.int64)
+    _check_rank(load().ials_rank_metrics(_ptr(ids), n_users, k, _ptr(hold_ptr), _ptr(hold_idx), kinds.size,
+                                         kinds.ctypes.data, ks.ctypes.data, _ptr(per_user), sums.ctypes.data,
+                                         counts.ctypes.data, _stream(stream)))
+    return sums, counts
