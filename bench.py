@@ -187,6 +187,57 @@ def matched_loss(p, epochs):
     return res
 
 
+RANK_K = 100
+RANK_METRICS = (("recall", 20), ("recall", 50), ("ndcg", 100))
+
+
+def ranking_bench(W, H, reps=3):
+    """Top-100 recommendation for every row of W against H (scoring on the matrix cores, then the
+    selection), timed with events on the current stream over `reps` calls after one warm-up."""
+    import torch
+    from paper_2110_14044_amd import rank_topk
+    rank_topk(W, H, RANK_K)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rank_topk(W, H, RANK_K)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    U, d = W.shape
+    I = H.shape[0]
+    return {"users": U, "items": I, "d": d, "k": RANK_K, "ms": ms, "users_per_s": U / ms * 1e3,
+            "score_tflops": 2.0 * U * I * d / ms / 1e9}
+
+
+def holdout_eval(p, epochs, n_users=10_000):
+    """Sec. 5.1's protocol on the synthetic matrix: train without n_users held-out users, fold
+    them in from 80 % of their items, rank every other item and measure Recall@20, Recall@50 and
+    NDCG@100 against the other 20 % (a random split: the numbers measure the pipeline, not the
+    quality of a model of real data)."""
+    import torch
+    import synth
+    from paper_2110_14044_amd import Trainer, rank_metrics, rank_topk
+    split = synth.holdout_split(p, n_users)
+    tr = Trainer(split.train, graph=True)
+    tr.epoch(epochs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wf = tr.foldin(split.fold_ptr, split.fold_idx, passes=3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ids, _ = rank_topk(Wf, tr.H, RANK_K, split.fold_ptr, split.fold_idx)
+    per, means, counts = rank_metrics(ids, split.hold_ptr, split.hold_idx, RANK_METRICS)
+    t2 = time.perf_counter()
+    tr.close()
+    out = {"held_out_users": int(split.users.size), "train_epochs": epochs, "foldin_s": t1 - t0,
+           "rank_and_metrics_s": t2 - t1}
+    for (name, k), m in zip(RANK_METRICS, means):
+        out[f"{name}@{k}"] = float(m)
+    return out
+
+
 def block_sweep(p, blocks, epochs):
     """Epoch time and training loss against the block size b on one workload, every b from the
     same W0, H0 (sec. 5.2.1: b = 1 is iCD, b = d is iALS, the cost per epoch is U-shaped in b
@@ -241,6 +292,9 @@ def main():
                     help="fold-in serving measurement beside the training epochs")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=2000)
+    ap.add_argument("--rank", choices=("on", "off", "only"), default="on",
+                    help="top-100 ranking of every user after training, and the holdout evaluation "
+                         "(only: the ranking of the initial embeddings, nothing else)")
     ap.add_argument("--block-sweep", default="",
                     help="comma-separated block sizes: report epoch time and loss per b on --workload, then exit")
     ap.add_argument("--sweep-epochs", type=int, default=4, help="timed epochs per block size of --block-sweep")
@@ -273,6 +327,14 @@ def main():
         return
 
     wl = synth.workload(args.workload)
+    if args.rank == "only":
+        torch.cuda.set_device(0)
+        p = synth.make_problem(args.workload)
+        W = torch.from_numpy(p.W0).cuda()
+        H = torch.from_numpy(p.H0).cuda()
+        print(json.dumps({"ranking": {"all_users": ranking_bench(W, H)}, "workload": wl.name, "dtype": "f32",
+                          "data": "synthetic"}))
+        return
     if args.block_sweep:
         blocks = [int(x) for x in args.block_sweep.split(",")]
         torch.cuda.set_device(0)
@@ -423,7 +485,16 @@ def main():
         cpu = {"value": work / t_cpu, "unit": "nnz·b/s", "cores": threads, "kind": "oracle", "sample": sample,
                "seconds": t_cpu}
 
+    ranking = None
+    if args.rank == "on":
+        log(f"[bench] ranking: top-{RANK_K} of every user")
+        ranking = {"all_users": ranking_bench(tr.W, tr.H)}
+        log(f"[bench] ranking {ranking['all_users']['ms']:.2f} ms for {p.num_users} users")
     tr.close()
+    if args.rank == "on":
+        log("[bench] holdout evaluation: 10,000 users held out, fold-in, top-100, Recall/NDCG")
+        ranking["holdout"] = holdout_eval(p, args.steps)
+        log(f"[bench] holdout {ranking['holdout']}")
     matched = None
     if args.matched_loss_epochs > 0:
         log(f"[bench] matched-loss comparison: fp32 vs bf16, {args.matched_loss_epochs} epochs")
@@ -444,6 +515,7 @@ def main():
         "autotune": tuned,
         "epoch_s": epoch_s, "epoch_s_profiled_eager": t_prof / args.steps, "loss_after": L,
         "roofline": roofline, "kernel_rates": kernel_rates, "cpu_baseline": cpu, "kernels": kern, "bf16_vs_fp32": matched, "serving": serving,
+        "ranking": ranking,
     }
     tr.close()
     print(json.dumps(out))

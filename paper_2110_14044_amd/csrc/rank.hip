@@ -110,12 +110,11 @@ __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, cons
         for (int a = 0; a < 4; ++a) {
             const int i = i_base + 16 * a + 4 * g;
             if (i >= I4) continue;
-            float4 v;
-            v.x = (i + 0 < I) ? acc[a][b][0] : -INFINITY;
-            v.y = (i + 1 < I) ? acc[a][b][1] : -INFINITY;
-            v.z = (i + 2 < I) ? acc[a][b][2] : -INFINITY;
-            v.w = (i + 3 < I) ? acc[a][b][3] : -INFINITY;
-            *reinterpret_cast<float4*>(srow + i) = v;
+            floatx4_r v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = (i + j < I) ? acc[a][b][j] : -INFINITY;
+            // streamed past the caches: the select reads the batch back from memory anyway
+            __builtin_nontemporal_store(v, reinterpret_cast<floatx4_r*>(srow + i));
         }
     }
 }
@@ -156,6 +155,22 @@ __device__ inline int lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
+// Scores of items 4 (t0 + 64 r + lane) + j (r, j < 4) of a row: four 16-byte loads in flight per
+// lane (-inf past the row); e[4 r + j].
+__device__ inline void load_row16(const float* srow, int n4, int t0, int lane, float (&e)[16]) {
+    floatx4_r v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = t0 + 64 * r + lane;
+        v[r] = t < n4 ? __builtin_nontemporal_load(reinterpret_cast<const floatx4_r*>(srow) + t)
+                      : floatx4_r{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[4 * r + j] = v[r][j];
+}
+
 // One wavefront per user of the batch; see the file comment.
 __global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int32_t nu, int32_t I4, int32_t k,
                                                 int64_t u0, int32_t* __restrict__ out_ids, float* __restrict__ out_sc) {
@@ -179,15 +194,13 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int
         const int nb = 1 << nbits;
         for (int b = lane; b < nb; b += 64) L.bins[b] = 0;
         lds_sync_wave();
-        for (int t0 = 0; t0 < n4; t0 += 64) {
-            const int t = t0 + lane;
-            const float4 v = t < n4 ? *reinterpret_cast<const float4*>(srow + 4 * (size_t)t)
-                                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
-            const float e[4] = {v.x, v.y, v.z, v.w};
+        for (int t0 = 0; t0 < n4; t0 += 256) {
+            float e[16];
+            load_row16(srow, n4, t0, lane, e);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t key = fkey(e[j]);
-                if (e[j] > -INFINITY && (key & pmask) == prefix) atomicAdd(&L.bins[(key >> shift) & dmask], 1u);
+            for (int c = 0; c < 16; ++c) {
+                const uint32_t key = fkey(e[c]);
+                if (e[c] > -INFINITY && (key & pmask) == prefix) atomicAdd(&L.bins[(key >> shift) & dmask], 1u);
             }
         }
         lds_sync_wave();
@@ -243,21 +256,18 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int
     // collect
     int count = 0;
     if (!ties) {
-        // every lane runs every iteration (the ballots below count the whole wavefront)
-        for (int t0 = 0; t0 < n4; t0 += 64) {
-            const int t = t0 + lane;
-            const float4 v = t < n4 ? *reinterpret_cast<const float4*>(srow + 4 * (size_t)t)
-                                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
-            const float e[4] = {v.x, v.y, v.z, v.w};
+        for (int t0 = 0; t0 < n4; t0 += 256) {
+            float e[16];
+            load_row16(srow, n4, t0, lane, e);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t key = fkey(e[j]);
-                const bool take = e[j] > -INFINITY && (take_all || key >= lower);
+            for (int c = 0; c < 16; ++c) {
+                const uint32_t key = fkey(e[c]);
+                const bool take = e[c] > -INFINITY && (take_all || key >= lower);
                 const uint64_t m = __ballot(take);
                 const int pos = count + lanes_below(m);
                 if (take && pos < kSelCap) {  // always true: the bucket was chosen to fit
                     L.c.key[pos] = key;
-                    L.c.id[pos] = 4 * t + j;
+                    L.c.id[pos] = 4 * (t0 + 64 * (c >> 2) + lane) + (c & 3);
                 }
                 count = std::min(kSelCap, count + (int)__popcll(m));
             }
@@ -265,21 +275,18 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int
     } else {
         // keys above the tie key (fewer than k), then equal keys in ascending id order up to k
         const uint32_t tk = prefix;
-        // every lane runs every iteration (the ballots below count the whole wavefront)
-        for (int t0 = 0; t0 < n4; t0 += 64) {
-            const int t = t0 + lane;
-            const float4 v = t < n4 ? *reinterpret_cast<const float4*>(srow + 4 * (size_t)t)
-                                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
-            const float e[4] = {v.x, v.y, v.z, v.w};
+        for (int t0 = 0; t0 < n4; t0 += 256) {
+            float e[16];
+            load_row16(srow, n4, t0, lane, e);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t key = fkey(e[j]);
-                const bool take = e[j] > -INFINITY && key > tk;
+            for (int c = 0; c < 16; ++c) {
+                const uint32_t key = fkey(e[c]);
+                const bool take = e[c] > -INFINITY && key > tk;
                 const uint64_t m = __ballot(take);
                 const int pos = count + lanes_below(m);
                 if (take && pos < k) {  // always true: fewer than k keys lie above the tie key
                     L.c.key[pos] = key;
-                    L.c.id[pos] = 4 * t + j;
+                    L.c.id[pos] = 4 * (t0 + 64 * (c >> 2) + lane) + (c & 3);
                 }
                 count = std::min(k, count + (int)__popcll(m));
             }
