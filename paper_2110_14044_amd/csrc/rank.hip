@@ -59,14 +59,21 @@ __device__ inline float fval(uint32_t k) {
 // ---------------------------------------------------------------------------------------------
 // S[u - u0][i] = <w_u, h_i> for u in [u0, u0 + nu), i in [0, I4) (-inf for i >= I), row pitch I4.
 // Workgroup: 4 wavefronts in 2 x 2, 128 items x 128 users; wavefront: 4 x 4 tiles of 16 x 16.
+// The grid is one-dimensional: 8 ipx n_ut workgroups for n_ut user tiles and ipx = ceil(n_it / 8).
 // Per 16 columns of f, lane (q = l % 16, g = l / 16) loads f in [f0 + 4g, f0 + 4g + 4) of 4 item
 // rows and 4 user rows and feeds component s to the MFMA k slot g of step s, in both operands.
 __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, const float* __restrict__ H, int32_t d,
                                                int64_t u0, int32_t nu, int32_t I, int32_t I4,
                                                float* __restrict__ S) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane & 15, g = lane >> 4;
-    const int i_base = blockIdx.x * 128 + (wave & 1) * 64;
-    const int u_base = blockIdx.y * 128 + (wave >> 1) * 64;
+    // Workgroups are dealt to the 8 XCDs round-robin (workgroup w runs on XCD w % 8); XCD x takes
+    // the item tiles [x ipx, (x + 1) ipx) for every user tile, so that its L2 holds 1/8 of H.
+    const int n_it = (I4 + 127) / 128, ipx = (n_it + 7) / 8;
+    const int w = blockIdx.x, xcd = w & 7, l = w >> 3;
+    const int it = xcd * ipx + l % ipx, ut = l / ipx;
+    if (it >= n_it || ut * 128 >= nu) return;  // padding workgroups of the last XCDs' ranges
+    const int i_base = it * 128 + (wave & 1) * 64;
+    const int u_base = ut * 128 + (wave >> 1) * 64;
     const float* hr[4];
     const float* wr[4];
 #pragma unroll
@@ -454,8 +461,9 @@ ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int3
     for (int64_t u0 = 0; u0 < n_users; u0 += ub) {
         const int32_t nu = (int32_t)std::min<int64_t>(ub, n_users - u0);
         if (I4 > 0) {
-            hipLaunchKernelGGL(k_score, dim3((unsigned)((I4 + 127) / 128), (unsigned)((nu + 127) / 128)), dim3(256), 0,
-                               st, W, H, d, u0, nu, n_items, I4, S);
+            const int64_t n_it = (I4 + 127) / 128, ipx = (n_it + 7) / 8, n_ut = (nu + 127) / 128;
+            hipLaunchKernelGGL(k_score, dim3((unsigned)(8 * ipx * n_ut)), dim3(256), 0, st, W, H, d, u0, nu, n_items,
+                               I4, S);
             if (excl_ptr)
                 hipLaunchKernelGGL(k_mask_excl, dim3((unsigned)((nu + 3) / 4)), dim3(256), 0, st, excl_ptr, excl_idx, u0,
                                    nu, n_items, I4, S);
