@@ -88,14 +88,22 @@ __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, cons
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_r{0.f, 0.f, 0.f, 0.f};
+    // the next 16 columns' operands are loaded before the current ones are multiplied
+    float4 av[4], bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool in = 4 * g < d;  // d is a multiple of 4
+        av[t] = in ? *reinterpret_cast<const float4*>(hr[t] + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+        bv[t] = in ? *reinterpret_cast<const float4*>(wr[t] + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     for (int f0 = 0; f0 < d; f0 += 16) {
-        const int f = f0 + 4 * g;
-        const bool in = f < d;  // d is a multiple of 4
-        float4 av[4], bv[4];
+        const int fn = f0 + 16 + 4 * g;
+        const bool inn = fn < d;
+        float4 an[4], bn[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            av[t] = in ? *reinterpret_cast<const float4*>(hr[t] + f) : make_float4(0.f, 0.f, 0.f, 0.f);
-            bv[t] = in ? *reinterpret_cast<const float4*>(wr[t] + f) : make_float4(0.f, 0.f, 0.f, 0.f);
+            an[t] = inn ? *reinterpret_cast<const float4*>(hr[t] + fn) : make_float4(0.f, 0.f, 0.f, 0.f);
+            bn[t] = inn ? *reinterpret_cast<const float4*>(wr[t] + fn) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -106,6 +114,11 @@ __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, cons
                 acc[a][b] = mfma16x4(av[a].z, bv[b].z, acc[a][b]);
                 acc[a][b] = mfma16x4(av[a].w, bv[b].w, acc[a][b]);
             }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            av[t] = an[t];
+            bv[t] = bn[t];
+        }
     }
     // accumulator layout: lane l, register j = (item row 4 g + j, user column q) of the tile
 #pragma unroll
@@ -120,8 +133,7 @@ __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, cons
             floatx4_r v;
 #pragma unroll
             for (int j = 0; j < 4; ++j) v[j] = (i + j < I) ? acc[a][b][j] : -INFINITY;
-            // streamed past the caches: the select reads the batch back from memory anyway
-            __builtin_nontemporal_store(v, reinterpret_cast<floatx4_r*>(srow + i));
+            *reinterpret_cast<floatx4_r*>(srow + i) = v;
         }
     }
 }
