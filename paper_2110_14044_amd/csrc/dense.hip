@@ -45,10 +45,7 @@ __global__ __launch_bounds__(256) void k_predict(int32_t U, int32_t d, const int
             const bool in = f >= p0 && f < p0 + bw;
             if (in == inside) s = fmaf(w[f], h[f], s);
         }
-        s += __shfl_xor(s, 8);
-        s += __shfl_xor(s, 4);
-        s += __shfl_xor(s, 2);
-        s += __shfl_xor(s, 1);
+        s = row_sum16(s);
         if (v && q16 == 0) out[k] = inside ? base[k] + s : s;
     }
 }
@@ -105,10 +102,7 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
                     s = fmaf(w[j].z, h[v][j].z, s);
                     s = fmaf(w[j].w, h[v][j].w, s);
                 }
-                s += __shfl_xor(s, 8);
-                s += __shfl_xor(s, 4);
-                s += __shfl_xor(s, 2);
-                s += __shfl_xor(s, 1);
+                s = row_sum16(s);
                 const int idx = 4 * (st + v) + g4;
                 if (q16 == 0 && idx < cnt) out[c0 + idx] = inside ? base[c0 + idx] + s : s;
             }

@@ -15,6 +15,18 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
+
+// Sum over the 16 lanes of each row of a wavefront (lanes 16r .. 16r + 15), returned in all 16:
+// DPP rotations within the row by 8, 4, 2 and 1 lanes.  Each step adds a value that equals the
+// xor-partner's (the partial sums are periodic in the row), so every lane ends with the same
+// value as an xor butterfly, without a trip through LDS.
+__device__ inline float row_sum16(float s) {
+    s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0x128, 0xf, 0xf, false));  // row_ror:8
+    s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0x124, 0xf, 0xf, false));  // row_ror:4
+    s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0x122, 0xf, 0xf, false));  // row_ror:2
+    s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0x121, 0xf, 0xf, false));  // row_ror:1
+    return s;
+}
 // Rows longer than the context's segment length (512 by default) are split into
 // segments of that many observations, each accumulated by its own wavefront (or
 // workgroup), then reduced in a fixed order.

@@ -75,13 +75,7 @@ __device__ inline int queue_next(int32_t* cursor, int lane) {
     if (lane == leader) it = atomicAdd(cursor, 1);
     return __builtin_amdgcn_readfirstlane(it);
 }
-__device__ inline float sum16(float s) {
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
-    return s;
-}
+__device__ inline float sum16(float s) { return row_sum16(s); }
 
 template <int NT>
 constexpr int ntiles() { return NT * (NT + 1) / 2; }

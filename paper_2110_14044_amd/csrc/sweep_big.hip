@@ -44,13 +44,7 @@ __device__ inline short bf16s(float f) {
 __device__ inline float readlane(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
-__device__ inline float sum16(float s) {
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
-    return s;
-}
+__device__ inline float sum16(float s) { return row_sum16(s); }
 __device__ inline void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
