@@ -18,6 +18,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -220,7 +221,10 @@ def holdout_eval(p, epochs, n_users=10_000):
     import synth
     from paper_2110_14044_amd import Trainer, rank_metrics, rank_topk
     split = synth.holdout_split(p, n_users)
-    tr = Trainer(split.train, graph=True)
+    train = split.train
+    if train.block > 64:  # the fold-in kernel takes blocks of up to 64 coordinates
+        train = dataclasses.replace(train, block=64)
+    tr = Trainer(train, graph=True)
     tr.epoch(epochs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -231,7 +235,8 @@ def holdout_eval(p, epochs, n_users=10_000):
     per, means, counts = rank_metrics(ids, split.hold_ptr, split.hold_idx, RANK_METRICS)
     t2 = time.perf_counter()
     tr.close()
-    out = {"held_out_users": int(split.users.size), "train_epochs": epochs, "foldin_s": t1 - t0,
+    out = {"held_out_users": int(split.users.size), "train_epochs": epochs, "block": train.block,
+           "foldin_s": t1 - t0,
            "rank_and_metrics_s": t2 - t1}
     for (name, k), m in zip(RANK_METRICS, means):
         out[f"{name}@{k}"] = float(m)
