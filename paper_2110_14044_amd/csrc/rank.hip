@@ -9,11 +9,14 @@
 //                 permuted order in both operands), items as the A operand so that each lane ends
 //                 with four consecutive items of one user and stores them as one 16-byte store
 //   k_mask_excl   S[u][i] = -inf for the items excluded for u (its fold-in / training items)
-//   k_select      one wavefront per user: MSB-first radix select on the order-preserving integer
-//                 key of the scores (digits of 11, 11 and 10 bits, histograms in LDS) until the
-//                 items at or above the current bucket fit the LDS candidate buffer, then one
-//                 pass collects them and a bitonic sort in LDS orders them by (score desc, id asc);
-//                 exact ties beyond the buffer are taken in ascending id order
+//   k_select      one wavefront per user: a histogram of an eighth of the row (every eighth run of
+//                 64 float4s) places a threshold that about 2k items should clear, and one pass
+//                 collects those into LDS; when fewer than k or more than the buffer clear it, an
+//                 MSB-first radix select on the order-preserving integer key of the scores (digits
+//                 of 11, 11 and 10 bits, histograms in LDS) runs until the items at or above the
+//                 current bucket fit the LDS candidate buffer, and one more pass collects them.
+//                 A bitonic sort in LDS orders the candidates by (score desc, id asc); exact ties
+//                 beyond the buffer are taken in ascending id order
 //   k_rank_metrics / k_metric_sums
 //                 Recall@k and NDCG@k per user in float64 (held-out lists searched by bisection),
 //                 then their sums over users in a fixed order
@@ -190,17 +193,9 @@ __device__ inline void load_row16(const float* srow, int n4, int t0, int lane, f
         for (int j = 0; j < 4; ++j) e[4 * r + j] = v[r][j];
 }
 
-// One wavefront per user of the batch; see the file comment.
-__global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int32_t nu, int32_t I4, int32_t k,
-                                                int64_t u0, int32_t* __restrict__ out_ids, float* __restrict__ out_sc) {
-    __shared__ SelLds lds_all[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int u = blockIdx.x * 4 + wave;
-    if (u >= nu) return;  // wave-uniform; no workgroup barriers below
-    SelLds& L = lds_all[wave];
-    const float* srow = S + (size_t)u * I4;
-    const int n4 = I4 / 4;
-
+// Radix select of the k largest of a row, then their collection: see the file comment.  The
+// candidates land in L.c (at most kSelCap); returns their number.
+__device__ int radix_collect(SelLds& L, const float* srow, int n4, int I4, int k, int lane) {
     uint32_t prefix = 0, pmask = 0;  // fixed high bits of the key and their mask
     int need = k;                    // items still to select inside the current bucket
     int chosen = 0;                  // items already known to be in the top k (above the bucket)
@@ -323,6 +318,92 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int
             count = std::min(k, count + (int)__popcll(m));
         }
     }
+    return count;
+}
+
+// Sampled threshold: the histogram of every eighth run of 64 float4s of the row places a key
+// that about 2k items should clear (at most 3/4 of the candidate buffer); one pass collects
+// every eligible item at or above it.  Returns the number collected when it is at least k and
+// fits the buffer (then the collected items hold the top k), else -1.
+__device__ int sampled_collect(SelLds& L, const float* srow, int n4, int k, int lane) {
+    if (n4 == 0) return -1;
+    for (int b = lane; b < kSelBins; b += 64) L.bins[b] = 0;
+    lds_sync_wave();
+    for (int t0 = 0; t0 < n4; t0 += 512) {
+        const int t = t0 + lane;
+        const floatx4_r v = t < n4 ? __builtin_nontemporal_load(reinterpret_cast<const floatx4_r*>(srow) + t)
+                                   : floatx4_r{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (v[j] > -INFINITY) atomicAdd(&L.bins[fkey(v[j]) >> 21], 1u);
+    }
+    lds_sync_wave();
+    constexpr int per = kSelBins / 64;
+    uint32_t s = 0;
+    for (int b = 0; b < per; ++b) s += L.bins[lane * per + b];
+    L.lane_sum[lane] = s;
+    lds_sync_wave();
+    uint32_t above_lane = 0, total = 0;
+    for (int l = 0; l < 64; ++l) {
+        const uint32_t x = L.lane_sum[l];
+        total += x;
+        if (l > lane) above_lane += x;
+    }
+    // sample items above the threshold: the target count scaled by the sampled fraction
+    const int64_t target = std::min(2 * k, 3 * kSelCap / 4);
+    const int m = (int)std::max<int64_t>(1, (target * (int64_t)total + 4ll * n4 - 1) / (4ll * n4));
+    int T = 0;
+    if ((int)total >= m) {
+        int t_l = -1;
+        if ((int)above_lane < m && (int)(above_lane + s) >= m) {
+            uint32_t acc = above_lane;
+            for (int b = per - 1; b >= 0; --b) {
+                acc += L.bins[lane * per + b];
+                if ((int)acc >= m) {
+                    t_l = lane * per + b;
+                    break;
+                }
+            }
+        }
+        const uint64_t found = __ballot(t_l >= 0);
+        T = __shfl(t_l, __builtin_ctzll(found));
+    }
+    lds_sync_wave();  // the bins are read before the candidates overwrite them
+    const uint32_t lower = (uint32_t)T << 21;
+    int count = 0;
+    for (int t0 = 0; t0 < n4; t0 += 256) {
+        float e[16];
+        load_row16(srow, n4, t0, lane, e);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const uint32_t key = fkey(e[c]);
+            const bool take = e[c] > -INFINITY && key >= lower;
+            const uint64_t mk = __ballot(take);
+            const int pos = count + lanes_below(mk);
+            if (take && pos < kSelCap) {
+                L.c.key[pos] = key;
+                L.c.id[pos] = 4 * (t0 + 64 * (c >> 2) + lane) + (c & 3);
+            }
+            count += (int)__popcll(mk);
+        }
+    }
+    lds_sync_wave();
+    return (count >= k && count <= kSelCap) ? count : -1;
+}
+
+// One wavefront per user of the batch; see the file comment.
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ S, int32_t nu, int32_t I4, int32_t k,
+                                                int64_t u0, int32_t* __restrict__ out_ids, float* __restrict__ out_sc) {
+    __shared__ SelLds lds_all[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int u = blockIdx.x * 4 + wave;
+    if (u >= nu) return;  // wave-uniform; no workgroup barriers below
+    SelLds& L = lds_all[wave];
+    const float* srow = S + (size_t)u * I4;
+    const int n4 = I4 / 4;
+
+    int count = sampled_collect(L, srow, n4, k, lane);
+    if (count < 0) count = radix_collect(L, srow, n4, I4, k, lane);
     lds_sync_wave();
 
     // bitonic sort of the candidates: descending key, ascending id; padding (key 0) sorts last
