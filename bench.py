@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--deal", choices=("auto", "static", "queue"), default="auto", help="row dealing of the row kernels")
     ap.add_argument("--autotune", action="store_true",
                     help="choose b, row dealing and segment length by measurement first (cached in --tune-cache)")
-    ap.add_argument("--tune-cache", default=os.path.join("gpurun_out", "autotune.json"))
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: the autotuner's own)")
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
                     help="arithmetic of the timed epochs (the bf16 form: bfloat16 Hessian and Gramian products)")
     ap.add_argument("--matched-loss-epochs", type=int, default=16,
@@ -317,8 +317,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of the sweep is "
-              "a design in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sharding of the sweep over several "
+              "GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
