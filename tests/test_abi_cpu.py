@@ -97,3 +97,32 @@ def test_null_server_and_foldin_calls_fail_cleanly(lib):
     assert lib.ials_server_poll(None, 1, 0, None, None, None, C.byref(n)) == binding.IALS_E_INVALID
     assert lib.ials_server_destroy(None) == binding.IALS_E_INVALID
     assert lib.ials_foldin(None, 0, None, None, None, 3, None) == binding.IALS_E_INVALID
+
+
+def test_rank_entry_points_reject_bad_arguments_before_device_work(lib):
+    E = binding.IALS_E_INVALID
+    f = lib.ials_rank_topk
+    # d not a multiple of 4, k out of [1, 512], negative sizes, missing pointers, half of an exclusion CSR
+    assert f(1, 4, 1, 5, 6, None, None, 3, 1, None, 0, None) == E
+    assert f(1, 4, 1, 5, 8, None, None, 0, 1, None, 0, None) == E
+    assert f(1, 4, 1, 5, 8, None, None, 513, 1, None, 0, None) == E
+    assert f(1, -1, 1, 5, 8, None, None, 3, 1, None, 0, None) == E
+    assert f(None, 4, 1, 5, 8, None, None, 3, 1, None, 0, None) == E
+    assert f(16, 4, 16, 5, 8, 16, None, 3, 16, None, 0, None) == E
+    assert f(3, 4, 16, 5, 8, None, None, 3, 16, None, 0, None) == E  # W not 16-byte aligned
+    assert lib.ials_rank_last_error()
+    # no users: nothing to do
+    assert f(None, 0, None, 5, 8, None, None, 3, None, None, 0, None) == binding.IALS_OK
+    g = lib.ials_rank_metrics
+    sums = (C.c_double * 2)()
+    counts = (C.c_int64 * 2)()
+    kinds = (C.c_int32 * 2)(0, 2)  # kind 2 is neither recall nor ndcg
+    ks = (C.c_int32 * 2)(5, 5)
+    assert g(1, 4, 10, 1, 1, 2, kinds, ks, 1, sums, counts, None) == E
+    kinds = (C.c_int32 * 2)(0, 1)
+    ks = (C.c_int32 * 2)(5, 11)  # k_m above the list length
+    assert g(1, 4, 10, 1, 1, 2, kinds, ks, 1, sums, counts, None) == E
+    ks = (C.c_int32 * 2)(5, 10)
+    assert g(None, 4, 10, None, None, 2, kinds, ks, None, sums, counts, None) == E
+    assert g(None, 0, 10, None, None, 2, kinds, ks, None, sums, counts, None) == binding.IALS_OK
+    assert list(sums) == [0.0, 0.0] and list(counts) == [0, 0]
