@@ -91,37 +91,43 @@ __global__ __launch_bounds__(256) void k_score(const float* __restrict__ W, cons
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_r{0.f, 0.f, 0.f, 0.f};
-    // the next 16 columns' operands are loaded before the current ones are multiplied
-    float4 av[4], bv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const bool in = 4 * g < d;  // d is a multiple of 4
-        av[t] = in ? *reinterpret_cast<const float4*>(hr[t] + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
-        bv[t] = in ? *reinterpret_cast<const float4*>(wr[t] + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    for (int f0 = 0; f0 < d; f0 += 16) {
-        const int fn = f0 + 16 + 4 * g;
-        const bool inn = fn < d;
-        float4 an[4], bn[4];
+    // Two sets of operands alternate: the next 16 columns are loaded while the current 16 are
+    // multiplied.  The loads have no branches (columns past d read column 0, and their item
+    // operand is zeroed where it is used), and the sets are never copied, so that waiting for
+    // the current operands does not also wait for the ones in flight.
+    floatx4_r a0[4], b0[4], a1[4], b1[4];
+    float z0, z1;
+    auto load = [&](int f0, floatx4_r* av, floatx4_r* bv, float& z) {
+        const int f = f0 + 4 * g;
+        const bool in = f < d;  // d is a multiple of 4
+        const int fc = in ? f : 0;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            an[t] = inn ? *reinterpret_cast<const float4*>(hr[t] + fn) : make_float4(0.f, 0.f, 0.f, 0.f);
-            bn[t] = inn ? *reinterpret_cast<const float4*>(wr[t] + fn) : make_float4(0.f, 0.f, 0.f, 0.f);
+            av[t] = *reinterpret_cast<const floatx4_r*>(hr[t] + fc);
+            bv[t] = *reinterpret_cast<const floatx4_r*>(wr[t] + fc);
         }
+        z = in ? 1.f : 0.f;
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the next MFMA block
+    };
+    auto mma = [&](floatx4_r* av, const floatx4_r* bv, float z) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[t] *= z;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                acc[a][b] = mfma16x4(av[a].x, bv[b].x, acc[a][b]);
-                acc[a][b] = mfma16x4(av[a].y, bv[b].y, acc[a][b]);
-                acc[a][b] = mfma16x4(av[a].z, bv[b].z, acc[a][b]);
-                acc[a][b] = mfma16x4(av[a].w, bv[b].w, acc[a][b]);
+                acc[a][b] = mfma16x4(av[a][0], bv[b][0], acc[a][b]);
+                acc[a][b] = mfma16x4(av[a][1], bv[b][1], acc[a][b]);
+                acc[a][b] = mfma16x4(av[a][2], bv[b][2], acc[a][b]);
+                acc[a][b] = mfma16x4(av[a][3], bv[b][3], acc[a][b]);
             }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            av[t] = an[t];
-            bv[t] = bn[t];
-        }
+    };
+    load(0, a0, b0, z0);
+    for (int f0 = 0; f0 < d; f0 += 32) {
+        load(f0 + 16, a1, b1, z1);
+        mma(a0, b0, z0);
+        load(f0 + 32, a0, b0, z0);
+        mma(a1, b1, z1);
     }
     // accumulator layout: lane l, register j = (item row 4 g + j, user column q) of the tile
 #pragma unroll
