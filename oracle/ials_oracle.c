@@ -113,14 +113,24 @@ void ora_predict(int32_t num_users, int32_t d, const int64_t* uptr, const int32_
 }
 
 /* G (d x bw, row-major) = sum_r x_r (x) x_{r, p0:p0+bw}: the partial Gramian of eq. 7.
- * With p0 = 0 and bw = d this is the full Gramian of eq. 4. */
+ * With p0 = 0 and bw = d this is the full Gramian of eq. 4.  Every entry is summed
+ * over r in ascending order; the rows r are walked in the outer loop so that X is
+ * read row by row (each thread owns a range of output rows f). */
 void ora_gramian(int32_t n, int32_t d, const double* X, int32_t p0, int32_t bw, double* G) {
-#pragma omp parallel for schedule(static)
-    for (int32_t f = 0; f < d; ++f) {
-        for (int32_t q = 0; q < bw; ++q) {
-            double s = 0.0;
-            for (int32_t r = 0; r < n; ++r) s += X[(size_t)r * d + f] * X[(size_t)r * d + p0 + q];
-            G[(size_t)f * bw + q] = s;
+#pragma omp parallel
+    {
+#pragma omp for schedule(static)
+        for (int32_t f = 0; f < d; ++f)
+            for (int32_t q = 0; q < bw; ++q) G[(size_t)f * bw + q] = 0.0;
+        /* the same static split of f as above: a thread only touches its own rows of G */
+#pragma omp for schedule(static)
+        for (int32_t f0 = 0; f0 < d; f0 += 16) {
+            const int32_t f1 = f0 + 16 < d ? f0 + 16 : d;
+            for (int32_t r = 0; r < n; ++r) {
+                const double* x = X + (size_t)r * d;
+                for (int32_t f = f0; f < f1; ++f)
+                    for (int32_t q = 0; q < bw; ++q) G[(size_t)f * bw + q] += x[f] * x[p0 + q];
+            }
         }
     }
 }

@@ -271,3 +271,55 @@ def test_pass_rows_equals_the_full_pass_on_those_rows(oracle_lib):
         assert np.array_equal(samp[rows], full[rows])
         rest = np.setdiff1d(np.arange(n), rows)
         assert np.array_equal(samp[rest], orig[rest])
+
+
+# ---------------------------------------------------------------- the epoch schedule (Alg. 3)
+
+def _scipy_epochs(p, n_epochs):
+    """Alg. 3's schedule written out with every block step taken by scipy: for each epoch, for
+    each block of the partition (contiguous, ascending, the last one shorter), every user's
+    block minimises the brute-force loss of eq. 2 with everything else fixed, then every item's
+    block does, against the users just updated.  Rows of one side are independent given the
+    other side (sec. 3.2), so they are minimised one by one from the state at the start of the
+    side's pass.  Returns the iterates and the brute-force loss after each epoch."""
+    y, a = bf.coo_labels(p)
+    W = p.W0.astype(np.float64).copy()
+    H = p.H0.astype(np.float64).copy()
+    L = lambda W_, H_: bf.loss_allpairs(p.user, p.item, y, a, W_, H_, p.alpha0, p.lam)
+    d, b = p.dim, p.block
+    losses = []
+    for _ in range(n_epochs):
+        for p0 in range(0, d, b):
+            bw = min(b, d - p0)
+            Wstart = W.copy()
+            for u in range(p.num_users):
+                def f(z, u=u):
+                    Wt = Wstart.copy()
+                    Wt[u, p0:p0 + bw] = z
+                    return L(Wt, H)
+                W[u, p0:p0 + bw] = _minimise(f, Wstart[u, p0:p0 + bw])
+            Hstart = H.copy()
+            for i in range(p.num_items):
+                def g(z, i=i):
+                    Ht = Hstart.copy()
+                    Ht[i, p0:p0 + bw] = z
+                    return L(W, Ht)
+                H[i, p0:p0 + bw] = _minimise(g, Hstart[i, p0:p0 + bw])
+        losses.append(L(W, H))
+    return W, H, np.array(losses)
+
+
+@pytest.mark.parametrize("d,b,epochs", [(6, 4, 1), (7, 3, 2)])
+def test_epoch_schedule_with_ragged_block_equals_scipy_block_minimisation(oracle_lib, d, b, epochs):
+    """oracle.epochs for b not dividing d (one ragged block; with d = 7, b = 3 three blocks,
+    the last of width 1) against the schedule of Alg. 3 carried out by scipy block minimisers
+    of the brute-force loss: a wrong block order, a stale Gramian, a wrong width of the
+    ragged block or a skipped pass would move the iterates (each planted in a copy of the
+    oracle fails this test)."""
+    p = _problem(40 + d, 5, 4, 12, d, b, labels=True)
+    csr, y, a, ys, as_ = _setup(p)
+    W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, b, p.alpha0, p.lam, epochs, ys, as_)
+    Wr, Hr, Lr = _scipy_epochs(p, epochs)
+    assert np.allclose(W, Wr, atol=1e-7), np.abs(W - Wr).max()
+    assert np.allclose(H, Hr, atol=1e-7), np.abs(H - Hr).max()
+    assert np.allclose(losses, Lr, rtol=1e-12)
