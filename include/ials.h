@@ -73,6 +73,14 @@ enum { IALS_FLAG_GRAPH = 1u };
  * Neither: static. */
 enum { IALS_FLAG_DEAL_QUEUE = 2u, IALS_FLAG_DEAL_STATIC = 4u };
 
+/* The passes a block size runs (sec. 3 and 4: iALS and iCD are the b = d and b = 1 ends of
+ * iALS++).  IALS_SOLVER_BLOCK: the block Newton steps of Alg. 3.  IALS_SOLVER_IALS (b = d):
+ * Alg. 1, every row solved against its dense normal equations (eq. 3) with no prediction
+ * cache and no dense gradient term; the rows of the side being solved are overwritten (zeroed
+ * first) during the pass.  IALS_SOLVER_ICD (b = 1): Alg. 2, scalar coordinate descent with
+ * the column g of the Gramian (no padded block, no factorisation). */
+typedef enum { IALS_SOLVER_BLOCK = 0, IALS_SOLVER_IALS = 1, IALS_SOLVER_ICD = 2 } ials_solver;
+
 typedef struct {
     int32_t num_users;          /* U >= 1 */
     int32_t num_items;          /* I >= 1 */
@@ -82,15 +90,18 @@ typedef struct {
     float alpha0;               /* weight of the all-pairs term, >= 0 */
     float lambda;               /* L2 weight, > 0 */
     int32_t precision;          /* ials_precision */
-    float chol_fallback_ratio;  /* tau: a row whose float32 pivots (the diagonal of D in
-                                   Hess = L D L^T, i.e. the squared Cholesky diagonal)
-                                   satisfy min < tau * max (or any pivot <= 0) is
-                                   refactored in float64; <= 0 selects 1e-6 */
+    float chol_fallback_ratio;  /* tau: a row whose smallest float32 pivot (the diagonal of D
+                                   in Hess = L D L^T, i.e. the squared Cholesky diagonal) is
+                                   below tau times the largest diagonal entry of its block
+                                   Hessian (a lower bound of 1 / condition number), or whose
+                                   pivots are not all positive, is refactored in float64;
+                                   <= 0 selects 1e-4; >= 1 redoes every row */
     uint32_t flags;             /* IALS_FLAG_* bits */
     uint32_t seg_len;           /* rows longer than this are accumulated in segments of this many
                                    observations (split-K); a multiple of 64 in [256, 65536];
                                    0 selects 512 */
-    uint64_t hbm_budget;        /* upper bound on library-owned device bytes; 0 = no bound */
+    uint64_t hbm_budget;        /* upper bound on the library's device bytes held at any time,
+                                   the temporaries of ials_create included; 0 = no bound */
 } ials_config;
 
 typedef struct {
@@ -115,6 +126,11 @@ typedef struct {
     uint64_t device_bytes;     /* library-owned device memory */
     int64_t foldin_requests;   /* rows folded in by ials_foldin since create */
     int64_t foldin_float64;    /* of those, rows redone in float64 */
+    uint64_t peak_device_bytes; /* most device memory held at once by the library, including the
+                                   temporaries of ials_create; an hbm_budget below it makes
+                                   ials_create fail with IALS_E_NOMEM */
+    int32_t solver;            /* ials_solver the block size selected */
+    int32_t reserved;
 } ials_stats;
 
 /*
@@ -243,7 +259,11 @@ IALS_API ials_status ials_profile_enable(ials_ctx* ctx, int32_t enable);
  * Synchronising. */
 IALS_API ials_status ials_profile_read(ials_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Enqueue subsequent work of ctx on another stream (hipStream_t; NULL = default). */
+/* Enqueue subsequent work of ctx on another stream (hipStream_t; NULL = default).
+ * Waits for the work already queued on the current stream first, so that the two
+ * streams never run passes over W, H and the prediction cache at the same time.
+ * A stream that ials_create made for the context is destroyed here.  IALS_E_INVALID
+ * for a NULL stream on a context with IALS_FLAG_GRAPH.  Synchronising. */
 IALS_API ials_status ials_set_stream(ials_ctx* ctx, void* hip_stream);
 
 /* Text of the last error on ctx (or of the last failed ials_create when ctx is NULL). */
@@ -271,7 +291,7 @@ typedef struct {
     int32_t passes;             /* sweeps per request, 0..1000 */
     int32_t max_slots;          /* requests admitted at once (queued, running or unpolled), >= 1 */
     int32_t streams;            /* batches in flight at once, 1..8; 0 selects 4 */
-    float chol_fallback_ratio;  /* tau as in ials_config; <= 0 selects 1e-6 */
+    float chol_fallback_ratio;  /* tau as in ials_config; <= 0 selects 1e-4 */
     uint64_t hbm_budget;        /* bytes of the device arena for request state; 0 selects 64 MiB */
 } ials_server_config;
 

@@ -23,6 +23,9 @@ IALS_E_HIP = -3
 IALS_E_NOT_SPD = -4
 IALS_E_BUSY = -5
 IALS_E_STATE = -6
+IALS_SOLVER_BLOCK = 0
+IALS_SOLVER_IALS = 1
+IALS_SOLVER_ICD = 2
 
 IALS_SIDE_USER = 0
 IALS_SIDE_ITEM = 1
@@ -58,7 +61,8 @@ class ials_stats(C.Structure):
                 ("long_rows_user", C.c_int32), ("long_rows_item", C.c_int32),
                 ("segments_user", C.c_int64), ("segments_item", C.c_int64),
                 ("fallback_rows", C.c_int64), ("passes", C.c_int64), ("device_bytes", C.c_uint64),
-                ("foldin_requests", C.c_int64), ("foldin_float64", C.c_int64)]
+                ("foldin_requests", C.c_int64), ("foldin_float64", C.c_int64),
+                ("peak_device_bytes", C.c_uint64), ("solver", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -13,7 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libials.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["csr.hip", "dense.hip", "sweep.hip", "sweep_big.hip", "foldin.hip", "serve.hip", "rank.hip", "api.hip"]
+SOURCES = ["csr.hip", "dense.hip", "sweep.hip", "sweep_big.hip", "icd.hip", "foldin.hip", "serve.hip", "rank.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -39,7 +39,7 @@ namespace ials {
 hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    if (c->budget && c->device_bytes + bytes > c->budget) return hipErrorOutOfMemory;
+    if (c->budget && c->device_bytes + c->tmp_bytes + bytes > c->budget) return hipErrorOutOfMemory;
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -47,7 +47,28 @@ hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes) {
     }
     c->owned.push_back(*p);
     c->device_bytes += bytes;
+    c->peak_bytes = std::max(c->peak_bytes, c->device_bytes + c->tmp_bytes);
     return hipSuccess;
+}
+
+hipError_t tmp_alloc(ials_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (c->budget && c->device_bytes + c->tmp_bytes + bytes > c->budget) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    c->tmp_bytes += bytes;
+    c->peak_bytes = std::max(c->peak_bytes, c->device_bytes + c->tmp_bytes);
+    return hipSuccess;
+}
+
+void tmp_free(ials_ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    c->tmp_bytes -= bytes == 0 ? 16 : bytes;
 }
 
 }  // namespace ials
@@ -68,7 +89,10 @@ ials_status fail(ials_ctx* c, ials_status s, const std::string& msg) {
         if (e_ != hipSuccess) {                                                            \
             g_create_error = std::string("device allocation of ") + std::to_string(bytes) + \
                              " bytes failed (" + hipGetErrorString(e_) + ")";              \
-            return IALS_E_NOMEM;                                                           \
+            if ((c)->budget && e_ == hipErrorOutOfMemory)                                  \
+                g_create_error += ": the HBM budget of " + std::to_string((c)->budget) +   \
+                                  " bytes would be exceeded";                              \
+            return ials::alloc_status(e_);                                                 \
         }                                                                                  \
     } while (0)
 
@@ -94,6 +118,15 @@ int32_t block_width(const ials_ctx* c, int32_t blk) {
     return std::min(c->b, c->d - p0);
 }
 
+// The solver a block size selects: b = d is Alg. 1 (each row solved exactly against the
+// dense normal equations, eq. 3), b = 1 is Alg. 2 (scalar coordinate descent), anything in
+// between the block steps of Alg. 3.
+int32_t solver_of(const ials_ctx* c) {
+    if (c->b == 1) return IALS_SOLVER_ICD;
+    if (c->b == c->d) return IALS_SOLVER_IALS;
+    return IALS_SOLVER_BLOCK;
+}
+
 ials_status run_pass(ials_ctx* c, int side, int32_t blk) {
     const int32_t p0 = blk * c->b;
     const int32_t bw = block_width(c, blk);
@@ -102,13 +135,30 @@ ials_status run_pass(ials_ctx* c, int side, int32_t blk) {
     const int32_t no = user ? c->I : c->U;
     float* X = user ? c->W : c->H;
     const int32_t n = user ? c->U : c->I;
+    const int32_t solver = solver_of(c);
+    if (solver == IALS_SOLVER_ICD) {
+        // Alg. 2: the Gramian column, the dense term and the step are inside the iCD pass
+        ials::launch_sweep(c, side, blk);
+        c->passes += 1;
+        IALS_HIP_TRY(c, hipGetLastError());
+        return IALS_OK;
+    }
     {
         ials::ProfScope ps(c, IALS_K_GRAM_USER + side);
         ials::launch_gramian_slab(c, Xo, no, p0, bw, c->B, c->G, true);
     }
     {
         ials::ProfScope ps(c, IALS_K_DENSE_USER + side);
-        ials::launch_dense(c, X, n, p0, bw);
+        if (solver == IALS_SOLVER_IALS) {
+            // Alg. 1: w = (alpha0 G + lambda I + sum alpha h h^T)^-1 sum alpha y h.  The row pass
+            // computes it as its Newton step from w = 0 with no dense term: the residual of every
+            // observation is then -y (the prediction cache is 0 when the block spans d), so the
+            // gradient is -sum alpha y h and the new row is 0 - delta.
+            ials::launch_fill(c->stream, X, (int64_t)n * c->d, 0.f);
+            ials::launch_fill(c->stream, c->R0, (int64_t)n * c->B, 0.f);
+        } else {
+            ials::launch_dense(c, X, n, p0, bw);
+        }
     }
     ials::launch_sweep(c, side, blk);
     c->passes += 1;
@@ -170,7 +220,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->B = cfg->block <= 64 ? (cfg->block + 15) / 16 * 16 : (cfg->block <= 128 ? 128 : 256);
     c->alpha0 = cfg->alpha0;
     c->lambda = cfg->lambda;
-    c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-6f;
+    c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-4f;
     c->precision = cfg->precision;
     c->seg_len = cfg->seg_len ? (int32_t)cfg->seg_len : ials::kSegLenDefault;
     c->nnz = S->nnz;
@@ -214,31 +264,47 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     // observations on the device (temporary copies when they come from the host)
     const int32_t *du = S->user, *di = S->item;
     const float *dy = S->y, *da = S->alpha;
-    std::vector<void*> tmp;
+    // (counted against the budget while held; freed once the index is built)
+    std::vector<std::pair<void*, size_t>> tmp;
     struct TmpFree {
-        std::vector<void*>& v;
+        ials_ctx* c;
+        std::vector<std::pair<void*, size_t>>& v;
         ~TmpFree() {
-            for (void* p : v) (void)hipFree(p);
+            (void)hipStreamSynchronize(c->stream);
+            for (auto& pb : v) ials::tmp_free(c, pb.first, pb.second);
         }
-    } tmp_free{tmp};
+    } tmp_free{c, tmp};
     if (S->memkind == IALS_MEM_HOST && nnz > 0) {
-        auto up = [&](const void* src, size_t bytes, void** dst) -> hipError_t {
-            hipError_t e = hipMalloc(dst, bytes);
-            if (e != hipSuccess) return e;
-            tmp.push_back(*dst);
-            return hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+        auto up = [&](const void* src, size_t bytes, void** dst) -> ials_status {
+            hipError_t e = ials::tmp_alloc(c, dst, bytes);
+            if (e != hipSuccess) {
+                g_create_error = "temporary device copy of the observations (" + std::to_string(bytes) +
+                                 " bytes) failed: " + hipGetErrorString(e);
+                return ials::alloc_status(e);
+            }
+            tmp.emplace_back(*dst, bytes);
+            e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) {
+                g_create_error = std::string("copy of the observations failed: ") + hipGetErrorString(e);
+                return IALS_E_HIP;
+            }
+            return IALS_OK;
         };
         void* p;
-        TRY_HIP_CREATE(up(S->user, sizeof(int32_t) * nnz, &p));
+        ials_status su = up(S->user, sizeof(int32_t) * nnz, &p);
+        if (su != IALS_OK) return su;
         du = (const int32_t*)p;
-        TRY_HIP_CREATE(up(S->item, sizeof(int32_t) * nnz, &p));
+        su = up(S->item, sizeof(int32_t) * nnz, &p);
+        if (su != IALS_OK) return su;
         di = (const int32_t*)p;
         if (has_y) {
-            TRY_HIP_CREATE(up(S->y, sizeof(float) * nnz, &p));
+            su = up(S->y, sizeof(float) * nnz, &p);
+            if (su != IALS_OK) return su;
             dy = (const float*)p;
         }
         if (has_a) {
-            TRY_HIP_CREATE(up(S->alpha, sizeof(float) * nnz, &p));
+            su = up(S->alpha, sizeof(float) * nnz, &p);
+            if (su != IALS_OK) return su;
             da = (const float*)p;
         }
     }
@@ -287,7 +353,10 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     }
 
     c->cur_block = 0;
-    ials::launch_predict(c, 0, false, c->yhat);
+    if (solver_of(c) == IALS_SOLVER_IALS)
+        ials::launch_fill(c->stream, c->yhat, c->nnz, 0.f);
+    else
+        ials::launch_predict(c, 0, false, c->yhat);
     TRY_HIP_CREATE(hipGetLastError());
     TRY_HIP_CREATE(hipStreamSynchronize(c->stream));
     guard.armed = false;
@@ -318,7 +387,19 @@ ials_status ials_destroy(ials_ctx* ctx) {
 
 ials_status ials_set_stream(ials_ctx* c, void* hip_stream) {
     if (check_ctx(c) != IALS_OK) return IALS_E_INVALID;
-    c->stream = (hipStream_t)hip_stream;
+    hipStream_t ns = (hipStream_t)hip_stream;
+    if ((c->flags & IALS_FLAG_GRAPH) && ns == nullptr)
+        return fail(c, IALS_E_INVALID, "a context with IALS_FLAG_GRAPH needs a non-NULL stream (graphs are not "
+                                       "captured on the NULL stream)");
+    if (ns == c->stream) return IALS_OK;
+    // work already queued on the old stream finishes before anything is queued on the new
+    // one (both touch W, H and the prediction cache); a stream the library made is released
+    IALS_HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->own_stream) {
+        IALS_HIP_TRY(c, hipStreamDestroy(c->stream));
+        c->own_stream = false;
+    }
+    c->stream = ns;
     return IALS_OK;
 }
 
@@ -364,7 +445,10 @@ ials_status launch_epoch(ials_ctx* c) {
     const int32_t nblocks = (c->d + c->b - 1) / c->b;
     {
         ials::ProfScope ps(c, IALS_K_PREDICT);
-        ials::launch_predict(c, 0, false, c->yhat);
+        if (solver_of(c) == IALS_SOLVER_IALS)
+            ials::launch_fill(c->stream, c->yhat, c->nnz, 0.f);  // Alg. 1 needs no predictions
+        else
+            ials::launch_predict(c, 0, false, c->yhat);
         c->cur_block = 0;
     }
     for (int32_t blk = 0; blk < nblocks; ++blk) {
@@ -488,6 +572,8 @@ ials_status ials_get_stats(ials_ctx* c, ials_stats* o) {
     o->fallback_rows = cnt[ials::CNT_FALLBACK_ROWS];
     o->passes = c->passes;
     o->device_bytes = c->device_bytes;
+    o->peak_device_bytes = c->peak_bytes;
+    o->solver = solver_of(c);
     o->foldin_requests = c->fold_requests;
     o->foldin_float64 = c->fold_float64;
     return IALS_OK;

@@ -296,16 +296,21 @@ hipError_t radix_sort(uint64_t* keys, int32_t* vals, uint64_t* kalt, int32_t* va
     return hipGetLastError();
 }
 
+// Temporaries of the index build, counted against the context's budget while held.
 struct TmpBuf {
-    std::vector<void*> ptrs;
+    ials_ctx* c;
+    std::vector<std::pair<void*, size_t>> ptrs;
+    explicit TmpBuf(ials_ctx* ctx) : c(ctx) {}
     ~TmpBuf() {
-        for (void* p : ptrs) (void)hipFree(p);
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& pb : ptrs) tmp_free(c, pb.first, pb.second);
     }
     template <typename T>
     hipError_t get(T** p, size_t count) {
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
-        if (e == hipSuccess) ptrs.push_back(q);
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = tmp_alloc(c, &q, bytes);
+        if (e == hipSuccess) ptrs.emplace_back(q, bytes);
         *p = (T*)q;
         return e;
     }
@@ -320,18 +325,18 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
     hipStream_t st = c->stream;
     const int64_t n = c->nnz;
     const int64_t U = c->U, I = c->I;
-    TmpBuf tmp;
+    TmpBuf tmp(c);
     uint64_t *keys, *kalt;
     int32_t *vals, *valt;
     uint32_t *hist, *sums;
     const int64_t nmax = std::max<int64_t>({n, U, I, 1});
     const int64_t nbmax = (nmax + kRsTile - 1) / kRsTile;
-    IALS_HIP_TRY(c, tmp.get(&keys, nmax));
-    IALS_HIP_TRY(c, tmp.get(&kalt, nmax));
-    IALS_HIP_TRY(c, tmp.get(&vals, nmax));
-    IALS_HIP_TRY(c, tmp.get(&valt, nmax));
-    IALS_HIP_TRY(c, tmp.get(&hist, 256 * nbmax));
-    IALS_HIP_TRY(c, tmp.get(&sums, (256 * nbmax + nmax + 2) / kScanTile + 2));
+    IALS_ALLOC_TRY(c, tmp.get(&keys, nmax));
+    IALS_ALLOC_TRY(c, tmp.get(&kalt, nmax));
+    IALS_ALLOC_TRY(c, tmp.get(&vals, nmax));
+    IALS_ALLOC_TRY(c, tmp.get(&valt, nmax));
+    IALS_ALLOC_TRY(c, tmp.get(&hist, 256 * nbmax));
+    IALS_ALLOC_TRY(c, tmp.get(&sums, (256 * nbmax + nmax + 2) / kScanTile + 2));
 
     // validation of ids and weights, before any index is derived from them
     if (n > 0) {
@@ -381,7 +386,7 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         SideIndex& s = c->side[sd];
         const int32_t nr = s.nrows;
         int32_t* nseg;
-        IALS_HIP_TRY(c, tmp.get(&nseg, nr + 1));
+        IALS_ALLOC_TRY(c, tmp.get(&nseg, nr + 1));
         hipLaunchKernelGGL(k_len_keys, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, c->seg_len, keys, vals, nseg);
         IALS_HIP_TRY(c, radix_sort(keys, vals, kalt, valt, nr, 32, hist, sums, st));
         IALS_HIP_TRY(c, hipMemcpyAsync(s.order, vals, sizeof(int32_t) * nr, hipMemcpyDeviceToDevice, st));
@@ -389,7 +394,7 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         uint64_t k0 = 0xFFFFFFFFull;
         if (nr > 0) IALS_HIP_TRY(c, hipMemcpyAsync(&k0, keys, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
         int32_t* scan;
-        IALS_HIP_TRY(c, tmp.get(&scan, nr + 1));
+        IALS_ALLOC_TRY(c, tmp.get(&scan, nr + 1));
         IALS_HIP_TRY(c, hipMemcpyAsync(scan, nseg, sizeof(int32_t) * nr, hipMemcpyDeviceToDevice, st));
         IALS_HIP_TRY(c, hipMemsetAsync(scan + nr, 0, sizeof(int32_t), st));
         IALS_HIP_TRY(c, scan_exclusive<int32_t>(scan, nr + 1, (int32_t*)sums, st));
@@ -400,9 +405,9 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         if (nr == 0) s.max_len = 0;
         s.nseg = total;
         if (total > 0) {
-            IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_row, sizeof(int32_t) * total));
-            IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_lo, sizeof(int64_t) * total));
-            IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_hi, sizeof(int64_t) * total));
+            IALS_ALLOC_TRY(c, dev_alloc(c, (void**)&s.seg_row, sizeof(int32_t) * total));
+            IALS_ALLOC_TRY(c, dev_alloc(c, (void**)&s.seg_lo, sizeof(int64_t) * total));
+            IALS_ALLOC_TRY(c, dev_alloc(c, (void**)&s.seg_hi, sizeof(int64_t) * total));
         }
         hipLaunchKernelGGL(k_seg_fill, dim3(nblk(nr, 256)), dim3(256), 0, st, s.ptr, nr, c->seg_len, scan, nseg, s.seg_first,
                            s.seg_row, s.seg_lo, s.seg_hi);
@@ -411,7 +416,7 @@ ials_status build_index(ials_ctx* c, const int32_t* d_user, const int32_t* d_ite
         // at one time gather from neighbouring partner rows (long rows' segments are narrow id
         // ranges) and share the L2
         if (total > 0) {
-            IALS_HIP_TRY(c, dev_alloc(c, (void**)&s.seg_order, sizeof(int32_t) * total));
+            IALS_ALLOC_TRY(c, dev_alloc(c, (void**)&s.seg_order, sizeof(int32_t) * total));
             hipLaunchKernelGGL(k_seg_keys, dim3(nblk(total, 256)), dim3(256), 0, st, s.seg_lo, s.col, total, keys, vals);
             IALS_HIP_TRY(c, radix_sort(keys, vals, kalt, valt, total, 64, hist, sums, st));
             IALS_HIP_TRY(c, hipMemcpyAsync(s.seg_order, vals, sizeof(int32_t) * total, hipMemcpyDeviceToDevice, st));

@@ -263,7 +263,11 @@ __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const fl
 // of tile ft is f = f0 + 4 m + ft, column n of tile qt is q = q0 + 4 n + qt).  The four
 // wavefronts of a block take interleaved groups of 16 rows of the chunk; their partials are
 // added in LDS in wavefront order, so one partial per block is written.
-__global__ __launch_bounds__(256, 3) void k_gram_vec(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
+// Two operand sets alternate: the rows of the next group are loaded while the current group
+// is multiplied.  The loads have no branches (rows past the chunk read its first row and
+// their weight z is 0), and the sets are never copied, so waiting for the current operands
+// does not wait for the ones in flight.
+__global__ __launch_bounds__(256, 2) void k_gram_vec(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
                                                   int32_t ncols, int32_t rows_per_chunk, float* __restrict__ part) {
     __shared__ floatx4 red[3][16][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
@@ -277,25 +281,37 @@ __global__ __launch_bounds__(256, 3) void k_gram_vec(int32_t n, int32_t d, const
         for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
     const float* xa = X + f0 + 4 * q16;
     const float* xb = X + p0 + q0 + 4 * q16;
-    for (int64_t rb = r0 + 16 * wave; rb < r1; rb += 64) {
-        float4 a[4], b[4];
+    floatx4 a0[4], b0[4], a1[4], b1[4];
+    float z0[4], z1[4];
+    auto load = [&](int64_t rb, floatx4* a, floatx4* b, float* z) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int64_t r = rb + 4 * s + g4;
-            const int64_t rr = r < r1 ? r : r0;  // rows past the chunk: a valid row with a zero weight
-            a[s] = *reinterpret_cast<const float4*>(xa + (size_t)rr * d);
-            b[s] = *reinterpret_cast<const float4*>(xb + (size_t)rr * d);
+            const bool in = r < r1;
+            const int64_t rr = in ? r : r0;
+            a[s] = *reinterpret_cast<const floatx4*>(xa + (size_t)rr * d);
+            b[s] = *reinterpret_cast<const floatx4*>(xb + (size_t)rr * d);
+            z[s] = in ? 1.f : 0.f;
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the next MFMA block
+    };
+    auto mma = [&](floatx4* a, const floatx4* b, const float* z) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bool in = rb + 4 * s + g4 < r1;
-            const float av[4] = {in ? a[s].x : 0.f, in ? a[s].y : 0.f, in ? a[s].z : 0.f, in ? a[s].w : 0.f};
-            const float bv[4] = {b[s].x, b[s].y, b[s].z, b[s].w};
+        for (int s = 0; s < 4; ++s) a[s] *= z[s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int ft = 0; ft < 4; ++ft)
 #pragma unroll
-                for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = mfma4(av[ft], bv[qt], acc[ft][qt]);
-        }
+                for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = mfma4(a[s][ft], b[s][qt], acc[ft][qt]);
+    };
+    int64_t rb = r0 + 16 * wave;
+    load(rb, a0, b0, z0);
+    for (; rb < r1; rb += 128) {
+        load(rb + 64, a1, b1, z1);
+        mma(a0, b0, z0);
+        load(rb + 128, a0, b0, z0);
+        mma(a1, b1, z1);
     }
     if (wave > 0) {
 #pragma unroll
@@ -408,7 +424,9 @@ __global__ __launch_bounds__(256) void k_dense(int32_t n, int32_t d, int32_t B, 
 // The same with 16-byte loads along f, for d a multiple of 16 and B a multiple of 64: lane
 // (q16, g4) loads f = fb + 4 g4 .. fb + 4 g4 + 3 of its row, and k-step s of a 16-wide f block
 // takes f = fb + 4 g4 + s (G is read in the same order, so the product is unchanged).  One
-// wavefront per 64 rows x 64 columns starting at column 64 * blockIdx.y.
+// wavefront per 64 rows x 64 columns starting at column 64 * blockIdx.y.  Two operand sets
+// alternate (the next 16 columns are loaded while the current ones are multiplied); loads past
+// d read column 0 with a zero weight, so they carry no branch.
 __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
                                                    const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
                                                    float lambda, float* __restrict__ R0) {
@@ -429,39 +447,37 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
         xr[rt] = X + (size_t)(r < n ? r : r0) * d + 4 * g4;  // rows past n: a valid row, never written
     }
     const float* gc = G + (size_t)(4 * g4) * B + qb + q16;
-    float4 a[4];
-    float b[4][4];
+    floatx4 a0[4], a1[4];
+    float b0[4][4], b1[4][4];
+    float z0, z1;
+    auto load = [&](int fb, floatx4* a, float (*b)[4], float& z) {
+        const bool in = fb < d;
+        const int f = in ? fb : 0;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const float4*>(xr[rt]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) b[s][t] = gc[(size_t)s * B + 16 * t];
-    for (int fb = 0; fb < d; fb += 16) {
-        // the next 16 columns' operands are loaded before this block is multiplied
-        const int fn = fb + 16 < d ? fb + 16 : fb;
-        float4 an[4];
-        float bn[4][4];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) an[rt] = *reinterpret_cast<const float4*>(xr[rt] + fn);
+        for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const floatx4*>(xr[rt] + f);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) bn[s][t] = gc[(size_t)(fn + s) * B + 16 * t];
+            for (int t = 0; t < 4; ++t) b[s][t] = gc[(size_t)(f + s) * B + 16 * t];
+        z = in ? 1.f : 0.f;
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the next MFMA block
+    };
+    auto mma = [&](floatx4* a, float (*b)[4], float z) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] *= z;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const float av = s == 0 ? a[rt].x : (s == 1 ? a[rt].y : (s == 2 ? a[rt].z : a[rt].w));
+            for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(av, b[s][t], acc[rt][t]);
-            }
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) a[rt] = an[rt];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) b[s][t] = bn[s][t];
+                for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(a[rt][s], b[s][t], acc[rt][t]);
+    };
+    load(0, a0, b0, z0);
+    for (int fb = 0; fb < d; fb += 32) {
+        load(fb + 16, a1, b1, z1);
+        mma(a0, b0, z0);
+        load(fb + 32, a0, b0, z0);
+        mma(a1, b1, z1);
     }
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
@@ -587,6 +603,30 @@ int chunk_rows_for(int64_t n, int64_t tiles, int64_t target_blocks, int64_t min_
 }
 
 }  // namespace
+
+namespace {
+// p[e] = v for e < n (a kernel rather than a memset node, so that it can be captured in graphs)
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+    const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+    for (int64_t e = e0; e < n; e += stride) {
+        if (e + 4 <= n && (reinterpret_cast<uintptr_t>(p + e) & 15u) == 0)
+            *reinterpret_cast<float4*>(p + e) = make_float4(v, v, v, v);
+        else
+            for (int64_t j = e; j < std::min<int64_t>(n, e + 4); ++j) p[j] = v;
+    }
+}
+}  // namespace
+
+void launch_fill(hipStream_t st, float* p, int64_t n, float v) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(8192, (n + 1023) / 1024);
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+void launch_gram_reduce(hipStream_t st, const float* part, int32_t nchunks, int64_t count, float* out) {
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, nchunks, count, out);
+}
 
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols) {
     const int64_t tiles = (int64_t)((d + 63) / 64) * ((ncols + 63) / 64);

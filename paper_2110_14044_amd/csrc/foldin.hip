@@ -285,7 +285,9 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                 }
             }
             float* Lt = fac + (size_t)blk * NTL * kTS;
-            // lower tiles plus alpha0 G[pi,pi] + lambda I (identity on the padding)
+            // lower tiles plus alpha0 G[pi,pi] + lambda I (identity on the padding); dmax: the
+            // largest diagonal entry over the real coordinates (the pivot test's reference)
+            float dmax = 0.f;
 #pragma unroll
             for (int I = 0; I < NT; ++I)
 #pragma unroll
@@ -294,10 +296,12 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int row = 16 * I + 4 * g4 + j, col = 16 * J + q16;
-                        if (row < bw && col < bw)
+                        if (row < bw && col < bw) {
                             c[j] += A.alpha0 * A.G[(size_t)(p0 + row) * d + p0 + col] + (row == col ? A.lambda : 0.f);
-                        else
+                            if (row == col) dmax = fmaxf(dmax, c[j]);
+                        } else {
                             c[j] += (row == col) ? 1.f : 0.f;
+                        }
                     }
                     tile_store(Lt + tid_of(I, J) * kTS, c, lane);
                 }
@@ -308,7 +312,10 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
             // lose L_IK L_JK^T, both on the matrix cores.
             float* tmp = tmp_all + wave * kTS;
             const int i16 = lane & 15;
-            float pmin = 3.0e38f, pmax = 0.f;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, m));
+            float pmin = 3.0e38f;
+            bool nonpos = false;  // a pivot that is not positive, NaN included (fminf skips NaNs)
 #pragma unroll 1
             for (int K = 0; K < NT; ++K) {
                 float* TK = Lt + tid_of(K, K) * kTS;
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                     const float piv = readlane(a[k], k);
                     if (16 * K + k < bw) {
                         pmin = fminf(pmin, piv);
-                        pmax = fmaxf(pmax, piv);
+                        nonpos = nonpos || !(piv > 0.f);
                     }
                     const float rs = piv > 0.f ? __builtin_amdgcn_rsqf(piv) : 0.f;
                     const float l = a[k] * rs;
@@ -362,7 +369,9 @@ __global__ __launch_bounds__(256) void k_foldin(FoldArgs A) {
                     }
                 wave_fence();
             }
-            if ((!(pmin > 0.f) || pmin < A.tau * pmax) && lane == 0) flag[0] = 1;
+            // (largest diagonal entry) / (smallest pivot) bounds the block's condition number from
+            // below (the pivots lie between the smallest eigenvalue and the diagonal entries)
+            if ((nonpos || !(pmin > 0.f) || pmin < A.tau * dmax) && lane == 0) flag[0] = 1;
             // X = L^-1 in place, row by row, each row's tiles in ascending column order:
             // X_II = Y_II (already there) and X_IJ = -Y_II sum_{J <= K < I} L_IK X_KJ.
 #pragma unroll 1

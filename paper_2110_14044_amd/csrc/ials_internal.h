@@ -123,7 +123,7 @@ struct FoldShape {
 struct ials_ctx {
     // configuration
     int32_t U = 0, I = 0, d = 0, b = 0, B = 0;  // B = b padded to a multiple of 16
-    float alpha0 = 0.f, lambda = 0.f, tau = 1e-6f;
+    float alpha0 = 0.f, lambda = 0.f, tau = 1e-4f;
     int32_t precision = 0;
     int32_t seg_len = ials::kSegLenDefault;
     int64_t nnz = 0;
@@ -158,7 +158,9 @@ struct ials_ctx {
     uint32_t flags = 0;
     bool own_stream = false;
     hipGraphExec_t epoch_exec = nullptr;  // captured epoch (IALS_FLAG_GRAPH)
-    uint64_t device_bytes = 0;
+    uint64_t device_bytes = 0;   // library-owned allocations held until destroy
+    uint64_t tmp_bytes = 0;      // create-time temporaries held now
+    uint64_t peak_bytes = 0;     // max of device_bytes + tmp_bytes so far
     uint64_t budget = 0;
     int64_t passes = 0;
 
@@ -258,11 +260,35 @@ size_t seg_part_floats_per_segment(int32_t B);
 // Group sums of segment partials (stride floats each) when A.seg_group > 1.
 void launch_seg_group(hipStream_t st, const SweepArgs& A, int32_t stride);
 size_t big_fallback_doubles(int32_t B);
+// Float64 redo of the rows a wide-block pass (B = 128 or 256) rejected (A.fb_scratch set).
+void launch_fallback_big(ials_ctx* c, const SweepArgs& A);
+
+// out[e] = sum over nchunks partials part[c][e] (count floats each), added in float64 in a fixed order.
+void launch_gram_reduce(hipStream_t st, const float* part, int32_t nchunks, int64_t count, float* out);
+// p[0 .. n) = v on the stream (a kernel, capturable in graphs).
+void launch_fill(hipStream_t st, float* p, int64_t n, float v);
+// One pass of the b = 1 specialisation (coordinate descent, Alg. 2) for coordinate blk.
+void launch_icd_pass(ials_ctx* c, int sd, int32_t blk);
 
 // Allocation helper that tracks the context's byte count and budget.
 hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes);
+// Create-time temporaries: counted against the same budget while they are held
+// (device_bytes + tmp_bytes never exceeds it), released by tmp_free.
+hipError_t tmp_alloc(ials_ctx* c, void** p, size_t bytes);
+void tmp_free(ials_ctx* c, void* p, size_t bytes);
+// IALS_E_NOMEM for an allocation failure or an exceeded budget, IALS_E_HIP otherwise.
+inline ials_status alloc_status(hipError_t e) { return e == hipErrorOutOfMemory ? IALS_E_NOMEM : IALS_E_HIP; }
 
 }  // namespace ials
+
+#define IALS_ALLOC_TRY(c, expr)                                                        \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (c)->err = std::string(#expr " failed: ") + hipGetErrorString(e_);         \
+            return ials::alloc_status(e_);                                             \
+        }                                                                              \
+    } while (0)
 
 #define IALS_HIP_TRY(c, expr)                                                          \
     do {                                                                               \

@@ -103,7 +103,7 @@ struct Batch {
 struct ials_server {
     ials::FoldShape fold;
     int device = 0;
-    float alpha0 = 0.f, lambda = 0.f, tau = 1e-6f;
+    float alpha0 = 0.f, lambda = 0.f, tau = 1e-4f;
     int32_t passes = 0, max_slots = 1, nstreams = 4;
     const float* H = nullptr;
     float* G = nullptr;
@@ -287,7 +287,7 @@ ials_status create_server(const ials_server_config* cfg, const float* H, ials_se
     s->fold = f;
     s->alpha0 = cfg->alpha0;
     s->lambda = cfg->lambda;
-    s->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-6f;
+    s->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-4f;
     s->passes = cfg->passes;
     s->max_slots = cfg->max_slots;
     s->nstreams = cfg->streams ? cfg->streams : 4;

@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "ials_internal.h"
@@ -92,7 +93,18 @@ __host__ __device__ constexpr int colmap(int p) { return FULL ? NT * (p & 15) + 
 template <int NT, bool VEC>
 __device__ inline void load_cols(const float* __restrict__ X, int d, int i, int p0, int bw, int q16, float* x) {
     const float* xr = X + (size_t)i * d + p0;
-    if constexpr (VEC && NT == 4) {
+    if constexpr (VEC && NT == 8) {
+        const float4 v0 = *reinterpret_cast<const float4*>(xr + 8 * q16);
+        const float4 v1 = *reinterpret_cast<const float4*>(xr + 8 * q16 + 4);
+        x[0] = v0.x;
+        x[1] = v0.y;
+        x[2] = v0.z;
+        x[3] = v0.w;
+        x[4] = v1.x;
+        x[5] = v1.y;
+        x[6] = v1.z;
+        x[7] = v1.w;
+    } else if constexpr (VEC && NT == 4) {
         const float4 v = *reinterpret_cast<const float4*>(xr + 4 * q16);
         x[0] = v.x;
         x[1] = v.y;
@@ -437,25 +449,45 @@ __device__ inline void ldl_panels(floatx4* acc, float& g, float* pan, int ln, fl
     }
 }
 
-template <int NT>
+// Largest diagonal entry of the Hessian over the real coordinates (lower tiles in p order,
+// the accumulator layout: lane (q16, g4) holds row 4 g4 + j, column q16 of each tile, so its
+// diagonal element of a diagonal tile, if any, is register q16 - 4 g4).  Every lane gets it.
+template <int NT, bool FULL>
+__device__ inline float diag_max(const floatx4* acc, int lane, int bw) {
+    const int q16 = lane & 15, jd = q16 - 4 * (lane >> 4);
+    float dmax = 0.f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const floatx4 v = acc[t * (t + 3) / 2];
+        const float e = jd == 0 ? v[0] : (jd == 1 ? v[1] : (jd == 2 ? v[2] : v[3]));
+        if (jd >= 0 && jd < 4 && colmap<NT, FULL>(16 * t + q16) < bw) dmax = fmaxf(dmax, e);
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, m));
+    return dmax;
+}
+
+template <int NT, bool FULL>
 __device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, const float* zero_lds, int ln, float tau,
                                  int my_col, int bw, float& x) {
     constexpr int B = 16 * NT;
     const float li = (ln < B) ? (float)ln : -1.f;  // lanes past the block never take a step
     float mypiv = 1.f;                             // lane k: the pivot of step k
+    // the pivots D_k of Hess = L D L^T lie between the smallest eigenvalue and the diagonal
+    // entries, so (largest diagonal entry) / (smallest pivot) bounds the condition number
+    // from below; a row is redone in float64 when it exceeds 1 / tau
+    const float dmax = diag_max<NT, FULL>(acc, ln, bw);
     ldl_panels<NT, 0>(acc, g, pan, ln, li, mypiv);
     // pivot check over the real (unpadded) coordinates
     const bool real = (ln < B) && (my_col < bw);
     float pmin = real ? mypiv : 3.0e38f;
-    float pmax = real ? mypiv : 0.f;
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        pmin = fminf(pmin, __shfl_xor(pmin, m));
-        pmax = fmaxf(pmax, __shfl_xor(pmax, m));
-    }
+    for (int m = 1; m < 64; m <<= 1) pmin = fminf(pmin, __shfl_xor(pmin, m));
     // identical in every lane after the reductions; made explicitly uniform so the
-    // row loop stays a uniform loop (its queue step needs the whole wave)
-    const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < tau * pmax)) ? 1 : 0);
+    // row loop stays a uniform loop (its queue step needs the whole wave).  A pivot that is
+    // not positive (NaN included: fminf skips NaNs) fails on its own.
+    const bool nonpos = __ballot(real && !(mypiv > 0.f)) != 0;
+    const int bad = __builtin_amdgcn_readfirstlane((nonpos || !(pmin > 0.f) || (pmin < tau * dmax)) ? 1 : 0);
     if (bad) return false;
     // w = D^-1 L^-1 g, then L^T x = w from the last column: x_k = w_k once every later column
     // has been applied, then w_i += (-L_ki) x_k for i < k (lane i reads row k of the panel
@@ -545,7 +577,7 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         int ln = lane;
         asm volatile("" : "+v"(ln));
         float w;
-        if (!ldl_solve<NT>(acc, g, pan, zero_lds, ln, A.tau, my_col, A.bw, w)) {
+        if (!ldl_solve<NT, FULL>(acc, g, pan, zero_lds, ln, A.tau, my_col, A.bw, w)) {
             // a pivot was rejected: the row is redone in float64
             if (lane == 0) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
@@ -555,6 +587,284 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
         }
         // w (lane p) = delta at block column colmap(p)
         if (lane < B && my_col < A.bw) A.X[(size_t)r * A.d + A.p0 + my_col] -= w;
+    }
+}
+
+// ---- Blocks of 65..128 coordinates (B = 128, NT = 8): one wavefront per row ----
+//
+// The 36 lower tiles of the Hessian stay in the wavefront's registers from the accumulation
+// (accumulate<> as in the narrow kernel, lane q16 holding 8 block columns) to the back
+// substitution; no other wavefront takes part in a row, so nothing waits on a workgroup
+// barrier.  The LDL^T factorisation goes panel by panel: the panel's 16 columns pass through
+// LDS to a lane-per-row layout relative to the panel (lane i holds panel row i and, for the
+// first four panels, panel row 64 + i), are eliminated with the DPP steps of the narrow
+// kernel (the forward substitution folded in), and return as -L into the same registers; the
+// trailing tiles take A_IJ -= L_IK diag(piv) L_JK^T on the matrix cores.  The back
+// substitution applies the off-diagonal -L tiles to the solved coordinates with matrix-core
+// products (column 0 of the product) and solves each 16 x 16 unit triangle from a copy of its
+// diagonal tile kept in LDS.
+struct W8Lds {
+    static constexpr int PAN = 0;               // the current panel: 128 rows at pitch kPS
+    static constexpr int DT = PAN + 128 * kPS;  // the 8 diagonal tiles of -L, 16 x 16 row-major
+    static constexpr int GL = DT + 8 * 256;     // [128] gradient, then z = L^-1 g
+    static constexpr int PV = GL + 128;         // [128] pivots
+    static constexpr int XS = PV + 128;         // [128] w = D^-1 z, then the solution
+    static constexpr int YS = XS + 128;         // [16] off-diagonal sums of one tile row
+    static constexpr int PER_WAVE = YS + 16;
+};
+
+template <int K, int KK>
+__device__ __forceinline__ void w8_steps(float* p1, float* p2, float& g1, float& g2, float* pvl, float li, int src,
+                                bool lead) {
+    if constexpr (KK < 16) {
+        const float piv = readlane(p1[KK], KK);
+        if (lead) pvl[16 * K + KK] = piv;
+        const float nr = __builtin_amdgcn_rcpf(-piv);
+        const float act = __builtin_amdgcn_fmed3f(li - (float)KK, 0.f, 1.f);  // 1 for the rows below KK
+        const float tn1 = p1[KK] * nr * act;                                 // -t_i
+        const float tn2 = K < 4 ? p2[KK] * nr : 0.f;                          // set 2: all below
+        if constexpr (KK < 15) {
+            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p1[KK])));
+            eliminate_cols<KK + 1, true>(p1, D, tn1);
+            if constexpr (K < 4) eliminate_cols<KK + 1, true>(p2, D, tn2);
+        }
+        const float gk = readlane(g1, KK);
+        g1 = fmaf(tn1, gk, g1);
+        p1[KK] = tn1;
+        if constexpr (K < 4) {
+            g2 = fmaf(tn2, gk, g2);
+            p2[KK] = tn2;
+        }
+        w8_steps<K, KK + 1>(p1, p2, g1, g2, pvl, li, src, lead);
+    }
+}
+
+// Panel K of the 128-wide LDL^T (see above); lds: this wavefront's W8Lds region.
+template <int K>
+__device__ __forceinline__ void w8_panels(floatx4* acc, float* lds, int lane) {
+    if constexpr (K < 8) {
+        const int q16 = lane & 15, g4 = lane >> 4;
+        float* PK = lds + W8Lds::PAN;
+        float* GL = lds + W8Lds::GL;
+        float* PV = lds + W8Lds::PV;
+        constexpr int NR = 128 - 16 * K;  // rows of the panel
+        // tiles (I, K) to LDS rows 16 (I - K) + row
+#pragma unroll
+        for (int I = K; I < 8; ++I) {
+            const int id = I * (I + 1) / 2 + K;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) PK[(16 * (I - K) + 4 * g4 + j) * kPS + q16] = acc[id][j];
+        }
+        wave_lds_fence();
+        const bool v1 = lane < NR;
+        const bool v2 = K < 4 && lane + 64 < NR;
+        float p1[16], p2[16];
+        const float* r1 = PK + (v1 ? lane : 0) * kPS;
+        const float* r2 = PK + (v2 ? lane + 64 : 0) * kPS;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const float4 a = *reinterpret_cast<const float4*>(r1 + 4 * c4);
+            p1[4 * c4 + 0] = v1 ? a.x : 0.f;
+            p1[4 * c4 + 1] = v1 ? a.y : 0.f;
+            p1[4 * c4 + 2] = v1 ? a.z : 0.f;
+            p1[4 * c4 + 3] = v1 ? a.w : 0.f;
+            if constexpr (K < 4) {
+                const float4 b = *reinterpret_cast<const float4*>(r2 + 4 * c4);
+                p2[4 * c4 + 0] = v2 ? b.x : 0.f;
+                p2[4 * c4 + 1] = v2 ? b.y : 0.f;
+                p2[4 * c4 + 2] = v2 ? b.z : 0.f;
+                p2[4 * c4 + 3] = v2 ? b.w : 0.f;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) p2[4 * c4 + c] = 0.f;
+            }
+        }
+        float g1 = v1 ? GL[16 * K + lane] : 0.f;
+        float g2 = v2 ? GL[16 * K + 64 + lane] : 0.f;
+        wave_lds_fence();
+        w8_steps<K, 0>(p1, p2, g1, g2, PV, v1 ? (float)lane : -1.f, (lane & 15) * 4, lane == 0);
+        // the panel as -L (zeros on and above the diagonal), the updated gradient, and a copy
+        // of the diagonal tile for the back substitution
+        if (v1) {
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                *reinterpret_cast<float4*>(PK + lane * kPS + 4 * c4) =
+                    make_float4(p1[4 * c4], p1[4 * c4 + 1], p1[4 * c4 + 2], p1[4 * c4 + 3]);
+            GL[16 * K + lane] = g1;
+        }
+        if (v2) {
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                *reinterpret_cast<float4*>(PK + (lane + 64) * kPS + 4 * c4) =
+                    make_float4(p2[4 * c4], p2[4 * c4 + 1], p2[4 * c4 + 2], p2[4 * c4 + 3]);
+            GL[16 * K + 64 + lane] = g2;
+        }
+        if (lane < 16) {
+            float* dt = lds + W8Lds::DT + K * 256 + lane * 16;
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                *reinterpret_cast<float4*>(dt + 4 * c4) =
+                    make_float4(p1[4 * c4], p1[4 * c4 + 1], p1[4 * c4 + 2], p1[4 * c4 + 3]);
+        }
+        wave_lds_fence();
+        // -L_IK (I > K) back into the registers of tile (I, K) for the back substitution
+#pragma unroll
+        for (int I = K + 1; I < 8; ++I) {
+            const int id = I * (I + 1) / 2 + K;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[id][j] = PK[(16 * (I - K) + 4 * g4 + j) * kPS + q16];
+        }
+        // trailing tiles: A_IJ -= L_IK diag(piv) L_JK^T for K < J <= I (the panel holds -L)
+        if constexpr (K + 1 < 8) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const float npm = -PV[16 * K + 4 * s4 + g4];
+                float op[8];
+#pragma unroll
+                for (int I = K + 1; I < 8; ++I) op[I] = PK[(16 * (I - K) + q16) * kPS + 4 * s4 + g4];
+#pragma unroll
+                for (int I = K + 1; I < 8; ++I) {
+                    const float a = op[I] * npm;
+#pragma unroll
+                    for (int J = K + 1; J <= I; ++J) {
+                        const int id = I * (I + 1) / 2 + J;
+                        acc[id] = mfma4(a, op[J], acc[id]);
+                    }
+                }
+            }
+        }
+        wave_lds_fence();
+        __builtin_amdgcn_sched_barrier(0);
+        w8_panels<K + 1>(acc, lds, lane);
+    }
+}
+
+// Back substitution for tile row K (from the last): x_K solves L_KK^T x_K = w_K - sum_{I>K}
+// L_IK^T x_I, with -L_IK in the registers of tile (I, K) and -L_KK in LDS.
+template <int K>
+__device__ __forceinline__ void w8_back(const floatx4* acc, float* lds, int lane) {
+    if constexpr (K >= 0) {
+        const int q16 = lane & 15, g4 = lane >> 4;
+        float* XS = lds + W8Lds::XS;
+        float* YS = lds + W8Lds::YS;
+        floatx4 y = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int I = K + 1; I < 8; ++I) {
+            const int id = I * (I + 1) / 2 + K;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float b = q16 == 0 ? XS[16 * I + 4 * g4 + s] : 0.f;
+                y = mfma4(acc[id][s], b, y);
+            }
+        }
+        if constexpr (K < 7) {
+            if (q16 == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) YS[4 * g4 + j] = y[j];
+            }
+        }
+        wave_lds_fence();
+        const int i = lane & 15;
+        float r = XS[16 * K + i] + (K < 7 ? YS[i] : 0.f);
+        const float* dt = lds + W8Lds::DT + K * 256;
+        float mc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) mc[k] = dt[k * 16 + i];  // -L_KK(k, i)
+#pragma unroll
+        for (int k = 15; k >= 0; --k) r = fmaf(mc[k], readlane(r, k), r);
+        wave_lds_fence();
+        if (lane < 16) XS[16 * K + lane] = r;
+        wave_lds_fence();
+        w8_back<K - 1>(acc, lds, lane);
+    }
+}
+
+template <bool FULL, bool TRANS, bool BF>
+__global__ __launch_bounds__(256, BF ? 1 : 2) void k_rows_w8(SweepArgs A) {
+    constexpr int NT = 8, B = 128, NTL = 36;
+    extern __shared__ float lds_w8[];
+    const int wave = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
+    float* lds = lds_w8 + wave * W8Lds::PER_WAVE;
+    for (int it = blockIdx.x * 4 + wave; it < A.nrows; it += gridDim.x * 4) {
+        const int r = A.order[it];
+        const int64_t lo = A.ptr[r], hi = A.ptr[r + 1];
+        int lane = lane0;  // laundered per row (see k_sweep_rows)
+        asm volatile("" : "+v"(lane));
+        const int q16 = lane & 15, g4 = lane >> 4;
+        floatx4 acc[NTL];
+#pragma unroll
+        for (int id = 0; id < NTL; ++id) acc[id] = *reinterpret_cast<const floatx4*>(A.dtiles + id * 256 + lane * 4);
+        float gp[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) gp[t] = 0.f;
+        const int sf = A.seg_first[r];
+        if (sf < 0) {
+            float own[NT], ownc[TRANS ? NT : 1];
+            load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
+            accumulate<NT, FULL, TRANS, BF, BF ? 4 : 2>(A, lo, hi, own, ownc, acc, gp, lane);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                gp[t] += __shfl_xor(gp[t], 16);
+                gp[t] += __shfl_xor(gp[t], 32);
+            }
+        } else {
+            const int ns = (int)((hi - lo + A.seg_len - 1) / A.seg_len);
+            for (int s = sf; s < sf + ns; s += A.seg_group) {
+                const float* P = A.seg_part + (size_t)s * seg_stride<NT>();
+                // six tiles' loads in flight at a time (all 36 at once would need 144 more registers)
+#pragma unroll
+                for (int id0 = 0; id0 < NTL; id0 += 6) {
+                    floatx4 part[6];
+#pragma unroll
+                    for (int u = 0; u < 6; ++u)
+                        part[u] = __builtin_nontemporal_load(
+                            reinterpret_cast<const floatx4*>(P + ((size_t)(id0 + u) * 64 + lane) * 4));
+#pragma unroll
+                    for (int u = 0; u < 6; ++u) acc[id0 + u] += part[u];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (g4 == 0) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) gp[t] += __builtin_nontemporal_load(P + NTL * 256 + 16 * t + q16);
+                }
+            }
+        }
+        float* GL = lds + W8Lds::GL;
+        if (g4 == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                GL[16 * t + q16] = gp[t] + A.R0[(size_t)r * B + colmap<NT, FULL>(16 * t + q16)];
+        }
+        wave_lds_fence();
+        const float dmax = diag_max<NT, FULL>(acc, lane, A.bw);
+        w8_panels<0>(acc, lds, lane);
+        // pivot check over the real (unpadded) coordinates, against the largest diagonal entry
+        // (see ldl_solve)
+        const float* PV = lds + W8Lds::PV;
+        const float pa = PV[lane], pb = PV[64 + lane];
+        const bool ra = colmap<NT, FULL>(lane) < A.bw, rb = colmap<NT, FULL>(64 + lane) < A.bw;
+        float pmin = fminf(ra ? pa : 3.0e38f, rb ? pb : 3.0e38f);
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) pmin = fminf(pmin, __shfl_xor(pmin, m));
+        const bool nonpos = __ballot((ra && !(pa > 0.f)) || (rb && !(pb > 0.f))) != 0;
+        const int bad = __builtin_amdgcn_readfirstlane((nonpos || !(pmin > 0.f) || (pmin < A.tau * dmax)) ? 1 : 0);
+        if (bad) {
+            if (lane == 0) {
+                const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
+                A.fb_list[pos] = r;
+            }
+            continue;
+        }
+        float* XS = lds + W8Lds::XS;
+        XS[lane] = GL[lane] * __builtin_amdgcn_rcpf(pa);
+        XS[64 + lane] = GL[64 + lane] * __builtin_amdgcn_rcpf(pb);
+        wave_lds_fence();
+        w8_back<7>(acc, lds, lane);
+        const float xa = XS[lane], xb = XS[64 + lane];
+        const int ca = colmap<NT, FULL>(lane), cb = colmap<NT, FULL>(64 + lane);
+        if (ca < A.bw) A.X[(size_t)r * A.d + A.p0 + ca] -= xa;
+        if (cb < A.bw) A.X[(size_t)r * A.d + A.p0 + cb] -= xb;
+        wave_lds_fence();
     }
 }
 
@@ -732,6 +1042,60 @@ void launch_sweep_prec(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bo
     }
 }
 
+template <bool FULL, bool TRANS, bool BF>
+void launch_w8_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+    hipStream_t st = c->stream;
+    const unsigned max_blocks = (unsigned)c->num_cu * 8;
+    if (s.nseg > 0) {
+        ProfScope ps(c, IALS_K_SEG_USER + sd);
+        hipLaunchKernelGGL((k_sweep_seg<8, FULL, TRANS, BF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
+                           dim3(256), 0, st, args);
+        launch_seg_group(st, args, seg_stride<8>());
+    }
+    if (s.nrows > 0) {
+        const size_t lds = sizeof(float) * 4 * W8Lds::PER_WAVE;
+        hipLaunchKernelGGL((k_make_dtiles<8, FULL>), dim3((ntiles<8>() * 256 + 255) / 256), dim3(256), 0, st, args.Dmat,
+                           args.dtiles);
+        {
+            ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
+            // static dealing over exactly the workgroups that are resident at once
+            static std::atomic<int> resident{0};
+            if (resident.load() == 0) {
+                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows_w8<FULL, TRANS, BF>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rows_w8<FULL, TRANS, BF>, 256, lds) != hipSuccess ||
+                    nb < 1)
+                    nb = 1;
+                resident.store(nb);
+            }
+            hipLaunchKernelGGL((k_rows_w8<FULL, TRANS, BF>),
+                               dim3(std::min<unsigned>((unsigned)(c->num_cu * resident.load()), (s.nrows + 3) / 4)),
+                               dim3(256), lds, st, args);
+        }
+        ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
+        launch_fallback_big(c, args);
+    }
+}
+
+template <bool BF>
+void launch_sweep_w8(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
+    const bool full = vec_ok<8>(A, A.p0, A.bw, A.Xo) && vec_ok<8>(A, A.p0, A.bw, A.X);
+    A.cur_full = vec_ok<8>(A, A.pc, A.bwc, A.Xo) && vec_ok<8>(A, A.pc, A.bwc, A.X);
+    A.fb_scratch = c->fb_scratch;
+    if (full) {
+        if (trans)
+            launch_w8_nt<true, true, BF>(c, A, s, sd);
+        else
+            launch_w8_nt<true, false, BF>(c, A, s, sd);
+    } else {
+        if (trans)
+            launch_w8_nt<false, true, BF>(c, A, s, sd);
+        else
+            launch_w8_nt<false, false, BF>(c, A, s, sd);
+    }
+}
+
 }  // namespace
 
 void launch_seg_group(hipStream_t st, const SweepArgs& A, int32_t stride) {
@@ -747,6 +1111,10 @@ size_t seg_part_floats_per_segment(int32_t B) {
 
 // One pass of block blk on side sd; the cache moves to blk if it is relative to another block.
 void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
+    if (c->b == 1) {  // scalar coordinate descent: no padded block, no factorisation
+        launch_icd_pass(c, sd, blk);
+        return;
+    }
     const SideIndex& s = c->side[sd];
     SweepArgs A;
     A.ptr = s.ptr;
@@ -787,7 +1155,12 @@ void launch_sweep(ials_ctx* c, int sd, int32_t blk) {
     const int64_t max_ns = (s.max_len + c->seg_len - 1) / c->seg_len;
     A.seg_group = max_ns > 8 ? (int32_t)std::ceil(std::sqrt((double)max_ns)) : 1;
     const bool trans = blk != c->cur_block;
-    if (c->B > 64)
+    if (c->B == 128) {  // one wavefront per row
+        if (c->precision == IALS_PREC_BF16)
+            launch_sweep_w8<true>(c, A, s, sd, trans);
+        else
+            launch_sweep_w8<false>(c, A, s, sd, trans);
+    } else if (c->B > 64)
         launch_sweep_big(c, A, s, sd, trans);
     else if (c->precision == IALS_PREC_BF16)
         launch_sweep_prec<true>(c, A, s, sd, trans);

@@ -63,7 +63,8 @@ struct BigLds {
     static constexpr int G = XW + NW * B;         // [B]       gradient, then z = L^-1 g
     static constexpr int SP = G + B;              // [2][NW][16] back-substitution partials
     static constexpr int OWN = SP + 2 * NW * 16;  // [2][B] the row's own values (pass block, cache block)
-    static constexpr int TOTAL = OWN + 2 * B;
+    static constexpr int DM = OWN + 2 * B;        // [NW] each wave's largest diagonal entry
+    static constexpr int TOTAL = DM + NW;
 };
 
 // x[t] = X[i][p0 + 16t + q16] (0 outside the block)
@@ -430,6 +431,22 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) gl[16 * t + q16] = gp[t] + A.R0[(size_t)r * B + 16 * t + q16];
         }
+        {
+            // largest diagonal entry over the real coordinates of this wave's diagonal tiles
+            // (lane (q16, g4) holds row 4 g4 + j, column q16 of a tile)
+            const int jd = q16 - 4 * g4;
+            float dm = 0.f;
+#pragma unroll
+            for (int m = 0; m <= NT; ++m) {
+                int I, J;
+                tile_of(m, I1, NT, I, J);
+                const float e = jd == 0 ? acc[m][0] : (jd == 1 ? acc[m][1] : (jd == 2 ? acc[m][2] : acc[m][3]));
+                if (I == J && jd >= 0 && jd < 4 && 16 * I + q16 < A.bw) dm = fmaxf(dm, e);
+            }
+#pragma unroll
+            for (int s2 = 1; s2 < 64; s2 <<= 1) dm = fmaxf(dm, __shfl_xor(dm, s2));
+            if (lane == 0) lds_big[L::DM + I1] = dm;
+        }
         __syncthreads();  // every wave is done with its staging before the tiles land on it
 #pragma unroll
         for (int m = 0; m <= NT; ++m) {
@@ -465,22 +482,25 @@ __global__ __launch_bounds__(NT * 32) void k_rows_big(SweepArgs A) {
             __syncthreads();
         }
         // pivot check over the real coordinates (every wave, from LDS)
-        float pmin = 3.0e38f, pmax = 0.f;
+        // against the largest diagonal entry of the Hessian: the pivots lie between the smallest
+        // eigenvalue and the diagonal entries, so the ratio bounds the condition number from below
+        float pmin = 3.0e38f, dmax = 0.f;
+        bool nonpos_l = false;  // NaN pivots too (fminf skips NaNs)
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             const int q = 64 * h + lane;
             const float v = pvl[q];
             if (q < A.bw) {
                 pmin = fminf(pmin, v);
-                pmax = fmaxf(pmax, v);
+                nonpos_l = nonpos_l || !(v > 0.f);
             }
         }
 #pragma unroll
-        for (int m = 1; m < 64; m <<= 1) {
-            pmin = fminf(pmin, __shfl_xor(pmin, m));
-            pmax = fmaxf(pmax, __shfl_xor(pmax, m));
-        }
-        const int bad = __builtin_amdgcn_readfirstlane((!(pmin > 0.f) || (pmin < A.tau * pmax)) ? 1 : 0);
+        for (int w = 0; w < L::NW; ++w) dmax = fmaxf(dmax, lds_big[L::DM + w]);
+        const bool nonpos = __ballot(nonpos_l) != 0;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) pmin = fminf(pmin, __shfl_xor(pmin, m));
+        const int bad = __builtin_amdgcn_readfirstlane((nonpos || !(pmin > 0.f) || (pmin < A.tau * dmax)) ? 1 : 0);
         if (bad) {
             if (lead && lane == 0) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
@@ -680,6 +700,13 @@ void launch_big_b(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool tr
 }  // namespace
 
 size_t big_fallback_doubles(int32_t B) { return (size_t)kFallbackBlocksBig * B * B; }
+
+void launch_fallback_big(ials_ctx* c, const SweepArgs& A) {
+    if (c->B == 128)
+        hipLaunchKernelGGL((k_fallback_big<8>), dim3(kFallbackBlocksBig), dim3(256), 0, c->stream, A);
+    else
+        hipLaunchKernelGGL((k_fallback_big<16>), dim3(kFallbackBlocksBig), dim3(256), 0, c->stream, A);
+}
 
 void launch_sweep_big(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans) {
     const bool bf = c->precision == IALS_PREC_BF16;

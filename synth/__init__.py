@@ -245,6 +245,16 @@ def small_problem(seed: int, num_users: int, num_items: int, nnz: int, dim: int,
                    f"small{seed}")
 
 
+def rank_one_table(seed: int, rows: int, dim: int, lo: float = 1.0, hi: float = 2.0) -> np.ndarray:
+    """Rows c_r v on one seeded direction v (|v| = 1, c_r ~ U(lo, hi)), float32: a table whose
+    Gramian has rank one, for problems whose block Hessians are singular up to the L2 term."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(dim)
+    v /= np.linalg.norm(v)
+    c = rng.uniform(lo, hi, size=rows)
+    return (c[:, None] * v[None, :]).astype(np.float32)
+
+
 def serving_requests(seed: int, n_requests: int, num_items: int = 41_000, mu: float = 3.5,
                      sigma: float = 1.2, lo: int = 1, hi: int = 2_000, zipf_s: float = 0.9):
     """Fold-in request histories: lengths lognormal(mu, sigma) clipped to [lo, hi] (no
