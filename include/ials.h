@@ -85,17 +85,20 @@ typedef struct {
     int32_t num_users;          /* U >= 1 */
     int32_t num_items;          /* I >= 1 */
     int32_t dim;                /* d >= 1 */
-    int32_t block;              /* b, 1 <= b <= min(d, 256) (b > 64 runs the workgroup-per-row
-                                   kernels with the block padded to 128 or 256) */
+    int32_t block;              /* b, 1 <= b <= min(d, 256): b = 1 runs coordinate descent
+                                   (Alg. 2), b = d full-row solves (Alg. 1); blocks of 65..128
+                                   are padded to 128 (one wavefront per row), of 129..256 to
+                                   256 (one workgroup per row) */
     float alpha0;               /* weight of the all-pairs term, >= 0 */
     float lambda;               /* L2 weight, > 0 */
     int32_t precision;          /* ials_precision */
     float chol_fallback_ratio;  /* tau: a row whose smallest float32 pivot (the diagonal of D
                                    in Hess = L D L^T, i.e. the squared Cholesky diagonal) is
                                    below tau times the largest diagonal entry of its block
-                                   Hessian (a lower bound of 1 / condition number), or whose
-                                   pivots are not all positive, is refactored in float64;
-                                   <= 0 selects 1e-4; >= 1 redoes every row */
+                                   Hessian (their ratio bounds 1 / condition number from
+                                   above), or whose pivots are not all positive, is
+                                   refactored in float64; <= 0 selects 1e-4; >= 1 redoes
+                                   every row */
     uint32_t flags;             /* IALS_FLAG_* bits */
     uint32_t seg_len;           /* rows longer than this are accumulated in segments of this many
                                    observations (split-K); a multiple of 64 in [256, 65536];
