@@ -376,6 +376,22 @@ IALS_API ials_status ials_rank_topk(const float* W, int64_t n_users, const float
                                     float* out_scores, int64_t score_buffer_bytes, void* stream);
 
 /*
+ * ials_rank_topk for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, hosts that forbid hipMalloc): the same arguments, kernels and
+ * results, with the score buffer taken from a fixed array of 64 MiB in device memory that
+ * the library holds on every GPU it runs on until the process ends (users are scored in
+ * batches whose scores fit it).  Allocates nothing and frees nothing.  Calls that overlap on
+ * one GPU (several streams or host threads at once) share that array and race; issue them
+ * one after another.  IALS_E_INVALID, before any device work, for the arguments
+ * ials_rank_topk rejects and for n_items above 16,777,216 (one user's scores would not fit);
+ * IALS_E_HIP if the array's device address cannot be obtained.  stream must belong to the
+ * current device.  Asynchronous.
+ */
+IALS_API ials_status ials_rank_topk_noalloc(const float* W, int64_t n_users, const float* H, int32_t n_items,
+                                            int32_t d, const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k,
+                                            int32_t* out_ids, float* out_scores, void* stream);
+
+/*
  * Ranking metrics of the holdout evaluation (sec. 5.1 names Recall@k and NDCG@k; the
  * definitions are those of the protocol it follows).  For ranked lists ids [n_users * k] (id -1:
  * no item) and held-out items T_u = hold_idx[hold_ptr[u] .. hold_ptr[u+1]) (DEVICE, ids

@@ -121,6 +121,8 @@ _SIGS = {
     "ials_server_last_error": (C.c_char_p, [C.c_void_p]),
     "ials_rank_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "ials_rank_topk_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                         C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ials_rank_metrics": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ials_rank_last_error": (C.c_char_p, []),
@@ -361,6 +363,13 @@ def ials_rank_topk(W, n_users: int, H, n_items: int, d: int, excl_ptr, excl_idx,
     """W, H, excl_ptr, excl_idx, out_ids, out_scores: device tensors (excl_* and out_scores may be None)."""
     _check_rank(load().ials_rank_topk(_ptr(W), n_users, _ptr(H), n_items, d, _ptr(excl_ptr), _ptr(excl_idx), k,
                                       _ptr(out_ids), _ptr(out_scores), score_buffer_bytes, _stream(stream)))
+
+
+def ials_rank_topk_noalloc(W, n_users: int, H, n_items: int, d: int, excl_ptr, excl_idx, k: int, out_ids,
+                           out_scores, stream=None) -> None:
+    """ials_rank_topk with the library's fixed score scratch (no device allocation)."""
+    _check_rank(load().ials_rank_topk_noalloc(_ptr(W), n_users, _ptr(H), n_items, d, _ptr(excl_ptr),
+                                              _ptr(excl_idx), k, _ptr(out_ids), _ptr(out_scores), _stream(stream)))
 
 
 def ials_rank_metrics(ids, n_users: int, k: int, hold_ptr, hold_idx, kinds, ks, per_user, stream=None):

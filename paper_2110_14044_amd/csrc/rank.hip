@@ -25,9 +25,17 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "ials.h"
+
+// Score buffer of ials_rank_topk_noalloc: a fixed array in device memory, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes its name to a
+// kernel (on the host it is only a stand-in for the symbol): it takes the device address
+// from hipGetSymbolAddress once per device and passes that.
+constexpr size_t kRankScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) float scratch[kRankScratchBytes / sizeof(float)];
 
 namespace {
 
@@ -530,13 +538,10 @@ __global__ __launch_bounds__(256) void k_metric_sums(const double* __restrict__ 
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-}  // namespace
-
-extern "C" {
-
-ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d,
-                           const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, int32_t* out_ids,
-                           float* out_scores, int64_t score_buffer_bytes, void* stream) {
+// Argument checks shared by both top-k entry points; on success *I4 is n_items rounded up to 4.
+ials_status rank_check(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d,
+                       const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, const int32_t* out_ids,
+                       int32_t* I4) {
     if (n_users < 0 || n_items < 0 || d < 1 || (d & 3) != 0 || k < 1 || k > kMaxK)
         return rank_fail(IALS_E_INVALID, "need n_users >= 0, n_items >= 0, d >= 1 a multiple of 4, 1 <= k <= 512");
     if (n_users == 0) return IALS_OK;
@@ -544,19 +549,15 @@ ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int3
         return rank_fail(IALS_E_INVALID, "W, H and out_ids must be given; excl_ptr and excl_idx together or neither");
     if (!aligned16(W) || !aligned16(H)) return rank_fail(IALS_E_INVALID, "W and H must be 16-byte aligned");
     if (n_items > INT32_MAX - 4) return rank_fail(IALS_E_INVALID, "too many items");
-    hipStream_t st = (hipStream_t)stream;
-    const int32_t I4 = (n_items + 3) & ~3;
-    if (score_buffer_bytes <= 0) score_buffer_bytes = int64_t(1) << 30;
-    const int64_t row_bytes = std::max<int64_t>(16, (int64_t)I4 * 4);
-    const int64_t ub = std::max<int64_t>(1, std::min<int64_t>(n_users, score_buffer_bytes / row_bytes));
-    if (ub * (int64_t)I4 > (int64_t(1) << 40)) return rank_fail(IALS_E_INVALID, "score buffer too large");
-    float* S = nullptr;
-    if (I4 > 0) {
-        if (hipMallocAsync((void**)&S, (size_t)(ub * I4) * sizeof(float), st) != hipSuccess) {
-            (void)hipGetLastError();
-            return rank_fail(IALS_E_NOMEM, "score buffer allocation failed");
-        }
-    }
+    *I4 = (n_items + 3) & ~3;
+    return IALS_OK;
+}
+
+// Scores, exclusions and selection for users [0, n_users) in batches of ub users whose scores
+// fit S (ub * I4 floats).
+void rank_batches(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d, int32_t I4,
+                  const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, int32_t* out_ids, float* out_scores,
+                  float* S, int64_t ub, hipStream_t st) {
     for (int64_t u0 = 0; u0 < n_users; u0 += ub) {
         const int32_t nu = (int32_t)std::min<int64_t>(ub, n_users - u0);
         if (I4 > 0) {
@@ -570,7 +571,78 @@ ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int3
         hipLaunchKernelGGL(k_select, dim3((unsigned)((nu + 3) / 4)), dim3(256), 0, st, S, nu, I4, k, u0, out_ids,
                            out_scores);
     }
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+ials_status scratch_on_current_device(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rank_fail(IALS_E_HIP, std::string("hipGetDevice failed: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return rank_fail(IALS_E_INVALID, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return rank_fail(IALS_E_HIP, std::string("hipGetSymbolAddress of the score scratch failed: ") +
+                                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return IALS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ials_status ials_rank_topk(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d,
+                           const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, int32_t* out_ids,
+                           float* out_scores, int64_t score_buffer_bytes, void* stream) {
+    int32_t I4 = 0;
+    ials_status s = rank_check(W, n_users, H, n_items, d, excl_ptr, excl_idx, k, out_ids, &I4);
+    if (s != IALS_OK || n_users == 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (score_buffer_bytes <= 0) score_buffer_bytes = int64_t(1) << 30;
+    const int64_t row_bytes = std::max<int64_t>(16, (int64_t)I4 * 4);
+    const int64_t ub = std::max<int64_t>(1, std::min<int64_t>(n_users, score_buffer_bytes / row_bytes));
+    if (ub * (int64_t)I4 > (int64_t(1) << 40)) return rank_fail(IALS_E_INVALID, "score buffer too large");
+    float* S = nullptr;
+    if (I4 > 0) {
+        if (hipMallocAsync((void**)&S, (size_t)(ub * I4) * sizeof(float), st) != hipSuccess) {
+            (void)hipGetLastError();
+            return rank_fail(IALS_E_NOMEM, "score buffer allocation failed");
+        }
+    }
+    rank_batches(W, n_users, H, n_items, d, I4, excl_ptr, excl_idx, k, out_ids, out_scores, S, ub, st);
     if (S) (void)hipFreeAsync(S, st);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rank_fail(IALS_E_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+    return IALS_OK;
+}
+
+ials_status ials_rank_topk_noalloc(const float* W, int64_t n_users, const float* H, int32_t n_items, int32_t d,
+                                   const int64_t* excl_ptr, const int32_t* excl_idx, int32_t k, int32_t* out_ids,
+                                   float* out_scores, void* stream) {
+    int32_t I4 = 0;
+    ials_status s = rank_check(W, n_users, H, n_items, d, excl_ptr, excl_idx, k, out_ids, &I4);
+    if (s != IALS_OK || n_users == 0) return s;
+    const int64_t row_bytes = std::max<int64_t>(16, (int64_t)I4 * 4);
+    if (row_bytes > (int64_t)kRankScratchBytes)
+        return rank_fail(IALS_E_INVALID, "one user's scores need " + std::to_string(row_bytes) +
+                                             " bytes, more than the fixed score scratch of " +
+                                             std::to_string(kRankScratchBytes) + " bytes (n_items <= " +
+                                             std::to_string(kRankScratchBytes / 4) + ")");
+    float* S = nullptr;
+    s = scratch_on_current_device(&S);
+    if (s != IALS_OK) return s;
+    const int64_t ub = std::min<int64_t>(n_users, (int64_t)kRankScratchBytes / row_bytes);
+    rank_batches(W, n_users, H, n_items, d, I4, excl_ptr, excl_idx, k, out_ids, out_scores, S, ub,
+                 (hipStream_t)stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rank_fail(IALS_E_HIP, std::string("launch failed: ") + hipGetErrorString(e));
     return IALS_OK;
