@@ -476,7 +476,7 @@ def cpu_baseline_sampled(p, frac=0.05, seed=7):
             "sample": sample, "seconds": t5 - t0, "epoch_s_estimate": est}
 
 
-def matched_loss(p, epochs):
+def matched_loss(p, epochs, deal="auto", seg_len=0):
     """Plain float32 form against the bfloat16 form on the same workload at the same b.  Each form
     runs `epochs` epochs from W0, H0; L* is the float32 form's loss after the last one.  Each form
     is charged the time of its epochs up to the first whose loss is within L*(1 + 1e-3) (the same
@@ -488,10 +488,10 @@ def matched_loss(p, epochs):
     from paper_2110_14044_amd import Trainer, binding
     out = {}
     for name, prec in (("fp32", binding.IALS_PREC_FP32), ("bf16", binding.IALS_PREC_BF16)):
-        warm = Trainer(p, precision=prec)
+        warm = Trainer(p, precision=prec, deal=deal, seg_len=seg_len)
         warm.epoch(1)
         warm.close()
-        tr = Trainer(p, precision=prec)
+        tr = Trainer(p, precision=prec, deal=deal, seg_len=seg_len)
         times, losses = [], []
         for t in range(epochs):
             torch.cuda.synchronize()
@@ -520,7 +520,7 @@ def matched_loss(p, epochs):
                      "epochs_to_threshold": None if e is None else e + 1,
                      "time_to_threshold_s": None if e is None else sum(ts[:e + 1]),
                      "loss_per_epoch": ls, "epoch_s": ts}
-        roof, rates, eroof = rooflines(p, name, out[name]["kernels"], 0, med)
+        roof, rates, eroof = rooflines(p, name, out[name]["kernels"], seg_len, med)
         res[name].update({"roofline": roof, "kernel_rates": rates, "epoch_roofline": eroof,
                           "kernels": out[name]["kernels"]})
     res["median_epoch_ratio_fp32_over_bf16"] = res["fp32"]["median_epoch_s"] / res["bf16"]["median_epoch_s"]
@@ -529,6 +529,42 @@ def matched_loss(p, epochs):
                                                           res["bf16"]["time_to_threshold_s"])
     res["loss_rel_diff_per_epoch"] = [abs(a - b) / b for a, b in zip(out["bf16"]["loss"], out["fp32"]["loss"])]
     return res
+
+
+def gramian_rates(p, reps=10):
+    """The Gramian of the larger table (eq. 4: X^T X, d x d, and one block slab of eq. 7) in both
+    arithmetic forms, timed with HIP events on the library's stream over `reps` calls after a
+    warm-up.  The full Gramian is a contraction of 2 N d^2 FLOP over N d floats (matrix-core
+    bound at d = 1024); a slab is 2 N d b FLOP over the same floats (HBM bound)."""
+    import torch
+    from paper_2110_14044_amd import Trainer, binding
+    N, d, b = p.num_users, p.dim, p.block
+    out = {}
+    for name, prec in (("fp32", binding.IALS_PREC_FP32), ("bf16", binding.IALS_PREC_BF16)):
+        tr = Trainer(p, precision=prec)
+        res = {}
+        for what, blk, flops in (("full", -1, 2.0 * N * d * d), ("slab", 0, 2.0 * N * d * b)):
+            cols = d if blk < 0 else b
+            G = torch.empty((d, cols), dtype=torch.float32, device="cuda")
+            binding.ials_gramian(tr.ctx, binding.IALS_MAT_W, blk, G)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                binding.ials_gramian(tr.ctx, binding.IALS_MAT_W, blk, G)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tf = flops / (ms * 1e-3) / 1e12
+            gbs = 4.0 * N * d / (ms * 1e-3) / 1e9
+            res[what] = {"ms": ms, "TFLOP/s": round(tf, 2), "matrix_peak": PEAK_MATRIX[name],
+                         "frac_of_matrix_peak": round(tf / PEAK_MATRIX[name], 4),
+                         "GB/s_of_X": round(gbs, 1), "frac_of_hbm": round(gbs / PEAK_HBM, 4)}
+        tr.close()
+        out[name] = res
+        log(f"[bench] Gramian of W ({N} x {d}) {name}: full {res['full']['ms']:.3f} ms "
+            f"({res['full']['TFLOP/s']} TFLOP/s), slab {res['slab']['ms']:.3f} ms")
+    return out
 
 
 def secondary_c2(args):
@@ -548,6 +584,7 @@ def secondary_c2(args):
         ranking["holdout"] = holdout_eval(p, 16)
     out = {"workload": f"{p.name}: {p.num_users} users x {p.num_items} items, {p.nnz} observations (y=alpha=1), "
                        f"d={p.dim}, b={p.block}, alpha0={p.alpha0}, lambda={p.lam}, float32, 16 epochs (graph)",
+           "bf16_vs_fp32": matched_loss(p, 16) if args.matched_loss_epochs > 0 else None,
            "epoch_s": leg["epoch_s"], "nnz_b_per_s": 2.0 * p.nnz * p.dim / leg["epoch_s"],
            "loss_after": leg["loss_after"], "epochs_trained": leg["epochs_trained"],
            "roofline": roof, "kernel_rates": rates, "epoch_roofline": eroof, "kernels": leg["kernels"],
@@ -562,6 +599,7 @@ def secondary_c3(args):
     import synth
     p = synth.make_problem("ml20m_like_d1024")
     res = matched_loss(p, args.matched_loss_epochs)
+    res["gramian"] = gramian_rates(p)
     res["workload"] = (f"{p.name}: {p.num_users} users x {p.num_items} items, {p.nnz} observations, d={p.dim}, "
                        f"b={p.block}, alpha0={p.alpha0}, lambda={p.lam}; float32 vs bfloat16 Hessian/Gramian "
                        f"products, {args.matched_loss_epochs} epochs each")
@@ -666,6 +704,13 @@ def main():
     value = 2.0 * p.nnz * p.dim / epoch_s
     roof, rates, eroof = rooflines(p, args.precision, leg["kernels"], seg_len, epoch_s)
     b_used = p.block
+    matched = None
+    if args.matched_loss_epochs > 0 and args.precision == "fp32":
+        log(f"[bench] {p.name}: float32 vs bfloat16 at matched loss, {args.steps} epochs")
+        matched = matched_loss(p, args.steps, deal=deal, seg_len=seg_len)
+        for k in ("fp32", "bf16"):
+            for drop in ("kernels", "kernel_rates"):
+                matched[k].pop(drop, None)
     cpu = None
     if not args.no_cpu_baseline:
         nb = math.ceil(p.dim / p.block)
@@ -697,6 +742,7 @@ def main():
         "autotune": tuned,
         "epoch_s": epoch_s, "loss_after": leg["loss_after"], "epochs_trained": leg["epochs_trained"],
         "roofline": roof, "epoch_roofline": eroof, "kernel_rates": rates, "cpu_baseline": cpu,
+        "bf16_vs_fp32": matched,
         "kernels": leg["kernels"], **secondary, "serving": serving,
     }
     print(json.dumps(out))

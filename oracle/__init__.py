@@ -33,7 +33,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libials_oracle.so")
+# IALS_ORACLE_LIB selects another build of the same source (the sanitizer tests use it)
+LIB_PATH = os.environ.get("IALS_ORACLE_LIB") or os.path.join(_HERE, "libials_oracle.so")
 _lib = None
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")

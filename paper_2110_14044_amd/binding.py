@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libials.so")
+# IALS_LIB selects another build of the same sources (the host sanitizer test uses it)
+LIB_PATH = os.environ.get("IALS_LIB") or os.path.join(_PKG, "libials.so")
 
 IALS_OK = 0
 IALS_E_INVALID = -1

@@ -338,6 +338,88 @@ __global__ __launch_bounds__(256, 2) void k_gram_vec(int32_t n, int32_t d, const
         }
 }
 
+// The bfloat16 form of k_gram_vec (same tiles, column mapping and output): rows are taken 32
+// at a time, lane group g4 holding rows 8 g4 .. 8 g4 + 7 of them, converted to bfloat16 (round
+// to nearest even, v_cvt_pk_bf16_f32) and multiplied with v_mfma_f32_16x16x32_bf16 (float32
+// accumulation): 16 matrix instructions per 32 rows instead of 128.  Two operand sets alternate
+// as in k_gram_vec; rows past the chunk read its first row and are zeroed before conversion.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__global__ __launch_bounds__(256, 2) void k_gram_vec_bf16(int32_t n, int32_t d, const float* __restrict__ X,
+                                                       int32_t p0, int32_t ncols, int32_t rows_per_chunk,
+                                                       float* __restrict__ part) {
+    __shared__ floatx4 red[3][16][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int f0 = blockIdx.x * 64, q0 = blockIdx.y * 64;
+    const int64_t r0 = (int64_t)blockIdx.z * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* xa = X + f0 + 4 * q16;
+    const float* xb = X + p0 + q0 + 4 * q16;
+    floatx4 a0[8], b0[8], a1[8], b1[8];
+    bool v0[8], v1[8];
+    auto load = [&](int64_t rb, floatx4* a, floatx4* b, bool* v) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t r = rb + 8 * g4 + j;
+            v[j] = r < r1;
+            const int64_t rr = v[j] ? r : r0;
+            a[j] = *reinterpret_cast<const floatx4*>(xa + (size_t)rr * d);
+            b[j] = *reinterpret_cast<const floatx4*>(xb + (size_t)rr * d);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the next MFMA block
+    };
+    auto mma = [&](const floatx4* a, const floatx4* b, const bool* v) {
+        bf16x8_t pa[4], pb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                pa[t][j] = (__bf16)(v[j] ? a[j][t] : 0.f);
+                pb[t][j] = (__bf16)b[j][t];
+            }
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt)
+                acc[ft][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[ft], pb[qt], acc[ft][qt], 0, 0, 0);
+    };
+    int64_t rb = r0 + 32 * wave;
+    load(rb, a0, b0, v0);
+    for (; rb < r1; rb += 256) {
+        load(rb + 128, a1, b1, v1);
+        mma(a0, b0, v0);
+        load(rb + 256, a0, b0, v0);
+        mma(a1, b1, v1);
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) red[wave - 1][4 * ft + qt][lane] = acc[ft][qt];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) acc[ft][qt] += red[w][4 * ft + qt][lane];
+    float* out = part + (size_t)blockIdx.z * d * ncols + q0 + 4 * q16;
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int f = f0 + 4 * (4 * g4 + j) + ft;
+            *reinterpret_cast<float4*>(out + (size_t)f * ncols) =
+                make_float4(acc[ft][0][j], acc[ft][1][j], acc[ft][2][j], acc[ft][3][j]);
+        }
+}
+
 // out[e] = sum over chunks of part[c][e] in float64.  A block owns 16 outputs; its
 // 16 thread rows each sum every 16th chunk, and the 16 partial sums of an
 // output are then added in a fixed order.
@@ -479,6 +561,93 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
         load(fb + 32, a0, b0, z0);
         mma(a1, b1, z1);
     }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = r0 + 16 * rt + 4 * g4 + j;
+                const int q = qb + 16 * t + q16;
+                if (r < n)
+                    R0[(size_t)r * B + q] =
+                        (q < bw) ? fmaf(alpha0, acc[rt][t][j], lambda * X[(size_t)r * d + p0 + q]) : 0.f;
+            }
+}
+
+// The same, with the G operand staged through LDS: the four wavefronts of a block take the
+// same 64 columns of G (and 4 x 64 different rows of X), so each 16 x 64 slice of G is loaded
+// once per block (one 16-byte load per thread) and read by every wavefront as 16-byte LDS reads
+// (stored column-major at a pitch of 20 floats: lane (q16, g4) of tile t reads the four
+// consecutive k-steps of column 16 t + q16).  Two slices alternate: the next one is loaded
+// while the current one is multiplied, one barrier per 16 columns of f.  Rows past n read row
+// 0 and are never written.
+constexpr int kGsPitch = 20;
+__global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
+                                                   const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
+                                                   float lambda, float* __restrict__ R0) {
+    __shared__ __align__(16) float gs[2][64 * kGsPitch];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q16 = lane & 15, g4 = lane >> 4;
+    const int qb = 64 * blockIdx.y;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* xr[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const int64_t r = r0 + 16 * rt + q16;
+        xr[rt] = X + (size_t)(r < n ? r : 0) * d + 4 * g4;
+    }
+    // staging: thread (row sr = tid / 16, quad sq = tid % 16) loads G[fb + sr][qb + 4 sq .. + 3]
+    const int sr = tid >> 4, sq = tid & 15;
+    const float* gsrc = G + (size_t)sr * B + qb + 4 * sq;
+    auto gload = [&](int fb) {
+        const int f = fb < d ? fb : 0;
+        return *reinterpret_cast<const floatx4*>(gsrc + (size_t)f * B);
+    };
+    auto gstore = [&](int buf, floatx4 v) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gs[buf][(4 * sq + c) * kGsPitch + sr] = v[c];
+    };
+    auto xload = [&](int fb, floatx4* a) {
+        const int f = fb < d ? fb : 0;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const floatx4*>(xr[rt] + f);
+    };
+    auto mma = [&](int buf, const floatx4* a) {
+        floatx4 b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = *reinterpret_cast<const floatx4*>(&gs[buf][(16 * t + q16) * kGsPitch + 4 * g4]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(a[rt][s], b[t][s], acc[rt][t]);
+    };
+    floatx4 a0[4], a1[4];
+    gstore(0, gload(0));
+    xload(0, a0);
+    __syncthreads();
+    // d is a multiple of 32 here: two slices per iteration, no tail
+    for (int fb = 0; fb < d; fb += 32) {
+        const floatx4 g1 = gload(fb + 16);
+        xload(fb + 16, a1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(0, a0);
+        gstore(1, g1);
+        __syncthreads();
+        const floatx4 g0 = gload(fb + 32);
+        xload(fb + 32, a0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(1, a1);
+        gstore(0, g0);
+        __syncthreads();
+    }
+    if (r0 >= n) return;
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -695,14 +864,17 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
-    if (!bf16 && d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0 &&
-        reinterpret_cast<uintptr_t>(X) % 16 == 0) {
+    if (d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         // full 64 x 64 tiles with 16-byte loads; four wavefronts per block, so a quarter of the
         // blocks (and of the partials the reduction reads) for the same number of wavefronts
         const int rv = chunk_rows_for(n, ft * qg, 512, 256);
         const int64_t cv = std::max<int64_t>(1, (n + rv - 1) / rv);
-        hipLaunchKernelGGL(k_gram_vec, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d, X, p0,
-                           ncols, rv, part);
+        if (bf16)
+            hipLaunchKernelGGL(k_gram_vec_bf16, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d,
+                               X, p0, ncols, rv, part);
+        else
+            hipLaunchKernelGGL(k_gram_vec, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d, X,
+                               p0, ncols, rv, part);
         const int64_t count = (int64_t)d * ncols;
         hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, (int32_t)cv, count, out);
         return;
@@ -736,6 +908,12 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
     if (n == 0) return;
     const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
     const int B = c->B;
+    if (B % 64 == 0 && c->d % 32 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(c->G) % 16 == 0) {
+        hipLaunchKernelGGL(k_dense_lds, dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X, c->G,
+                           p0, bw, c->alpha0, c->lambda, c->R0);
+        return;
+    }
     if (B % 64 == 0 && c->d % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         hipLaunchKernelGGL(k_dense_vec, dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X, c->G, p0,
                            bw, c->alpha0, c->lambda, c->R0);

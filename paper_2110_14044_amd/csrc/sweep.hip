@@ -48,13 +48,12 @@ __device__ inline floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 // bfloat16 (round to nearest even) of four floats, packed as the 4-element operand of
-// v_mfma_f32_16x16x16_bf16 (element v stands for observation v of this lane's four).
-__device__ inline unsigned bf16_bits(float f) {
-    const unsigned u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
+// v_mfma_f32_16x16x16_bf16 (element v stands for observation v of this lane's four); the
+// conversions are the hardware's v_cvt_pk_bf16_f32, two floats per instruction.
 __device__ inline shortx4 bf16x4(float a, float b, float c, float d) {
-    return shortx4{(short)bf16_bits(a), (short)bf16_bits(b), (short)bf16_bits(c), (short)bf16_bits(d)};
+    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+    const bf16x4_t v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+    return __builtin_bit_cast(shortx4, v);
 }
 __device__ inline floatx4 mfma_bf16(shortx4 a, shortx4 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);

@@ -76,6 +76,22 @@ def test_bf16_gramian():
     tr.close()
 
 
+def test_bf16_gramian_at_the_d1024_shape():
+    """The full Gramian (eq. 4, d x d) and a block slab (eq. 7) of the 136,000 x 1,024 user table
+    with bfloat16 products on the matrix cores (16x16x32) and float32 accumulation, against the
+    float64 oracle.  Bar: 1e-2 relative (each product carries a relative rounding error of at most
+    2^-8 from the two bfloat16 operands)."""
+    p = synth.make_problem("ml20m_like_d1024")
+    tr = gpu_trainer(p, precision=BF16)
+    G = host(tr.gramian(0, -1))
+    Gb = host(tr.gramian(0, 3))
+    tr.close()
+    e = rel(G, oracle.gramian(p.W0))
+    eb = rel(Gb, oracle.gramian(p.W0, 3 * p.block, p.block))
+    say(f"bf16 Gramian 136000 x 1024: full {e:.2e}, block 3 {eb:.2e}")
+    assert e < 1e-2 and eb < 1e-2
+
+
 def test_bf16_bitwise_deterministic():
     p = synth.small_problem(230, 2000, 100, 40_000, 64, 32, zipf_s=0.9, std=0.1)
     outs = []
