@@ -36,6 +36,18 @@ struct CreateGuard {
 
 namespace ials {
 
+int resident_per_cu(OccCache& cache, const void* kernel, int threads, size_t lds, bool set_lds, int fallback) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= OccCache::kDevices) return fallback;
+    int nb = cache.v[dev].load(std::memory_order_relaxed);
+    if (nb > 0) return nb;
+    if (set_lds && hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fallback;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) nb = fallback;
+    cache.v[dev].store(nb, std::memory_order_relaxed);
+    return nb;
+}
+
 hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
@@ -325,7 +337,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     TRY_ALLOC(c, c->fb_list, sizeof(int32_t) * nmax);
     size_t gp = 0;
     for (int32_t n : {c->U, c->I})
-        for (int32_t nc : {c->B, c->d}) gp = std::max(gp, ials::gram_part_floats_needed(n, c->d, nc));
+        for (int32_t nc : {c->B, c->d}) gp = std::max(gp, ials::gram_part_floats_needed(n, c->d, nc, c->precision == IALS_PREC_BF16));
     c->gram_part_floats = gp;
     TRY_ALLOC(c, c->gram_part, sizeof(float) * gp);
     const int64_t nseg = std::max(us.nseg, is.nseg);

@@ -420,6 +420,148 @@ __global__ __launch_bounds__(256, 2) void k_gram_vec_bf16(int32_t n, int32_t d, 
         }
 }
 
+// ---- Full Gramian in bfloat16 (X^T X, d a multiple of 256): LDS-staged 256 x 256 tiles ----
+//
+// A workgroup of eight wavefronts forms one lower 256 x 256 tile (I >= J) of X^T X over one
+// chunk of rows.  Per stage of 32 rows every thread loads an 8-row x 4-column block of the
+// tile's two column strips (float32, 16-byte loads, the next stage's loads in flight while the
+// current stage is multiplied), rounds it to bfloat16 (round to nearest even) and stores each
+// column's 8 values as one 16-byte LDS write, so that LDS holds, per column, the stage's 32
+// rows in order (a pitch of 40 bfloat16 spreads the 16-byte accesses over all banks).  Wavefront
+// (wf, wq) multiplies columns 128 wf .. +127 of strip I by columns 64 wq .. +63 of strip J:
+// 8 x 4 tiles of v_mfma_f32_16x16x32_bf16 per stage, each operand one 16-byte LDS read.  A
+// diagonal tile reads both operands from strip I.  The 256-wide edge quarters the strip reads
+// per product of the 64-wide tiles, which is what bounds the register-only kernel above.
+// Workgroups of one chunk sit on the same XCD (blocks are dealt to XCDs round-robin), so the
+// chunk's rows come from HBM once and from that XCD's L2 for the other tiles.
+constexpr int kGLT = 256;                      // tile edge
+constexpr int kGLK = 32;                       // rows per stage
+constexpr int kGLP = 40;                       // LDS pitch of one column, in bfloat16
+constexpr int kGLStrip = kGLT * kGLP;          // bfloat16 per strip
+constexpr size_t kGLLds = 4 * kGLStrip * 2;    // two stages x two strips, in bytes
+constexpr int kGLTileFloats = kGLT * kGLT;
+
+int gram_lds_tiles(int32_t d) {
+    const int T = d / kGLT;
+    return T * (T + 1) / 2;
+}
+int gram_lds_chunks(int64_t n, int32_t d) {
+    const int tiles = gram_lds_tiles(d);
+    int64_t chunks = std::max(1, 256 / tiles);
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (n + kGLK - 1) / kGLK));
+    return (int)chunks;
+}
+
+__global__ __launch_bounds__(512, 1) void k_gram_bf16_lds(int32_t n, int32_t d, const float* __restrict__ X,
+                                                          int32_t tiles, int32_t chunks, int32_t per_xcd,
+                                                          int32_t rows_per_chunk, float* __restrict__ part) {
+    extern __shared__ __align__(16) __bf16 gl_lds[];
+    // blocks b and b + 8 share an XCD: consecutive (chunk, tile) pairs go to the same XCD
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int pair = xcd * per_xcd + slot;
+    if (pair >= tiles * chunks) return;
+    const int chunk = pair / tiles, tile = pair - chunk * tiles;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+    const int J = tile - I * (I + 1) / 2;
+    const bool diag = I == J;
+    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, q16 = lane & 15, g4 = lane >> 4;
+    // loader role: strip s (0: columns of I, 1: columns of J), row group rg, column group cg
+    const int s = t >> 8, rg = t & 3, cg = (t >> 2) & 63;
+    const bool loader = !(diag && s == 1);
+    // rows at or past r1 read as zeros: the buffer's range ends at row r1 (byte offsets are 32-bit,
+    // the launcher checks that every row of X fits)
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), (short)0, (int)(r1 * d * 4), 0x00020000);
+    const uint32_t col_bytes = (uint32_t)((s == 0 ? I : J) * kGLT + 4 * cg) * 4;
+    // the next stage's rows are loaded while the current stage is multiplied
+    float4 va[8];
+    auto load = [&](float4* v, int64_t k0) {
+        if (!loader) return;
+        const uint32_t o = (uint32_t)(k0 + 8 * rg) * (uint32_t)(4 * d) + col_bytes;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            v[j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, o + (uint32_t)(j * 4 * d), 0, 0));
+    };
+    auto store = [&](const float4* v, int buf) {
+        if (!loader) return;
+        __bf16* base = gl_lds + (2 * buf + s) * kGLStrip + (4 * cg) * kGLP + 8 * rg;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            bf16x8_t w;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[j] = (__bf16)(c == 0 ? v[j].x : (c == 1 ? v[j].y : (c == 2 ? v[j].z : v[j].w)));
+            *reinterpret_cast<bf16x8_t*>(base + c * kGLP) = w;
+        }
+    };
+
+    const int wf = wave >> 2, wq = wave & 3;
+    floatx4 acc[8][4];
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto mma = [&](int buf) {
+        const __bf16* A = gl_lds + (2 * buf) * kGLStrip + (128 * wf + q16) * kGLP + 8 * g4;
+        const __bf16* B = gl_lds + (2 * buf + (diag ? 0 : 1)) * kGLStrip + (64 * wq + q16) * kGLP + 8 * g4;
+        bf16x8_t b[4];
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) b[qt] = *reinterpret_cast<const bf16x8_t*>(B + 16 * qt * kGLP);
+#pragma unroll
+        for (int ft = 0; ft < 8; ++ft) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(A + 16 * ft * kGLP);
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt)
+                acc[ft][qt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[qt], acc[ft][qt], 0, 0, 0);
+        }
+    };
+    const int nst = (int)std::max<int64_t>(0, (r1 - r0 + kGLK - 1) / kGLK);
+    auto k0_of = [&](int st) { return r0 + (int64_t)st * kGLK; };
+    if (nst > 0) {
+        load(va, k0_of(0));
+        store(va, 0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        if (st + 1 < nst) load(va, k0_of(st + 1));
+        mma(st & 1);
+        if (st + 1 < nst) store(va, (st + 1) & 1);
+        __syncthreads();
+    }
+    // partials in the register layout: ((wave * 8 + ft) * 4 + qt) * 64 + lane, four floats each
+    float* out = part + ((size_t)chunk * tiles + tile) * kGLTileFloats;
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt)
+            *reinterpret_cast<floatx4*>(out + ((size_t)((wave * 8 + ft) * 4 + qt) * 64 + lane) * 4) = acc[ft][qt];
+}
+
+// G (d x d) from the partials of k_gram_bf16_lds: each element of a lower tile summed over the
+// chunks in float64 in chunk order, written at (f, q) and mirrored to (q, f); in a diagonal tile
+// only the elements on or below the diagonal are taken, so G is exactly symmetric.
+__global__ __launch_bounds__(256) void k_gram_lds_reduce(const float* __restrict__ part, int32_t tiles, int32_t chunks,
+                                                         int32_t d, float* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)tiles * kGLTileFloats) return;
+    const int tile = (int)(e / kGLTileFloats), o = (int)(e - (int64_t)tile * kGLTileFloats);
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+    const int J = tile - I * (I + 1) / 2;
+    const int r = o & 3, lane = (o >> 2) & 63, qt = (o >> 8) & 3, ft = (o >> 10) & 7, w = o >> 13;
+    const int f = kGLT * I + 128 * (w >> 2) + 16 * ft + 4 * (lane >> 4) + r;
+    const int q = kGLT * J + 64 * (w & 3) + 16 * qt + (lane & 15);
+    if (I == J && f < q) return;
+    double sum = 0.0;
+    for (int c = 0; c < chunks; ++c) sum += (double)part[((size_t)c * tiles + tile) * kGLTileFloats + o];
+    const float g = (float)sum;
+    G[(size_t)f * d + q] = g;
+    G[(size_t)q * d + f] = g;
+}
+
 // out[e] = sum over chunks of part[c][e] in float64.  A block owns 16 outputs; its
 // 16 thread rows each sum every 16th chunk, and the 16 partial sums of an
 // output are then added in a fixed order.
@@ -797,11 +939,14 @@ void launch_gram_reduce(hipStream_t st, const float* part, int32_t nchunks, int6
     hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(count, 16)), dim3(256), 0, st, part, nchunks, count, out);
 }
 
-size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols) {
+size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols, bool bf16) {
     const int64_t tiles = (int64_t)((d + 63) / 64) * ((ncols + 63) / 64);
     const int rows = chunk_rows_for(n, tiles, 2048, 64);
     const int64_t chunks = (n + rows - 1) / rows;
-    return (size_t)std::max<int64_t>(chunks, 1) * d * ncols;
+    size_t need = (size_t)std::max<int64_t>(chunks, 1) * d * ncols;
+    if (bf16 && ncols == d && d % kGLT == 0)
+        need = std::max(need, (size_t)gram_lds_chunks(n, d) * gram_lds_tiles(d) * kGLTileFloats);
+    return need;
 }
 
 // inside == false: c->yhat becomes the cache relative to block blk; inside == true:
@@ -864,6 +1009,21 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     const int rows = chunk_rows_for(n, ft * qg, 2048, 64);
     const int64_t chunks = std::max<int64_t>(1, (n + rows - 1) / rows);
     dim3 grid((unsigned)ft, (unsigned)qg, (unsigned)chunks);
+    if (bf16 && p0 == 0 && bw == d && ncols == d && d % kGLT == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+        ((int64_t)n + 2 * kGLK) * d * 4 < ((int64_t)1 << 31)) {
+        // the full Gramian: LDS-staged 256 x 256 lower tiles, partials summed in float64
+        const int tiles = gram_lds_tiles(d), nch = gram_lds_chunks(n, d);
+        int64_t rows = (n + nch - 1) / nch;
+        rows = std::max<int64_t>(kGLK, (rows + kGLK - 1) / kGLK * kGLK);
+        const int per_xcd = (tiles * nch + 7) / 8;
+        static OccCache occ;
+        (void)resident_per_cu(occ, reinterpret_cast<const void*>(&k_gram_bf16_lds), 512, kGLLds, true, 1);
+        hipLaunchKernelGGL(k_gram_bf16_lds, dim3((unsigned)(8 * per_xcd)), dim3(512), kGLLds, st, n, d, X, tiles, nch,
+                           per_xcd, (int32_t)rows, part);
+        hipLaunchKernelGGL(k_gram_lds_reduce, dim3(nblk((int64_t)tiles * kGLTileFloats, 256)), dim3(256), 0, st, part,
+                           tiles, nch, d, out);
+        return;
+    }
     if (d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         // full 64 x 64 tiles with 16-byte loads; four wavefronts per block, so a quarter of the
         // blocks (and of the partials the reduction reads) for the same number of wavefronts

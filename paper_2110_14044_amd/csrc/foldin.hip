@@ -546,10 +546,9 @@ size_t lds_fac_bytes(int32_t nb, int32_t B) {
 
 template <int NT, bool GFAC>
 hipError_t launch_nt(hipStream_t st, const FoldShape& f, const FoldArgs& a) {
-    // the dynamic LDS limit is per kernel; set once (thread-safe static initialisation)
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_foldin<NT, GFAC>),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFoldLdsMax);
-    if (attr != hipSuccess) return attr;
+    // raises the kernel's dynamic-LDS limit on this device the first time (the limit is per device)
+    static OccCache occ;
+    (void)resident_per_cu(occ, reinterpret_cast<const void*>(&k_foldin<NT, GFAC>), 256, kFoldLdsMax, true, 1);
     hipLaunchKernelGGL((k_foldin<NT, GFAC>), dim3((unsigned)a.m), dim3(256), f.lds_bytes, st, a);
     return hipGetLastError();
 }

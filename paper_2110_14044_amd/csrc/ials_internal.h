@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -246,7 +247,7 @@ void launch_sweep(ials_ctx* c, int side, int32_t blk);
 // The pass for blocks wider than 64 coordinates (B = 128 or 256).
 void launch_sweep_big(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bool trans);
 ials_status launch_loss(ials_ctx* c);
-size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols);
+size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols, bool bf16);
 // out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats);
 // bf16: bfloat16 operands on the matrix cores, float32 partials, float64 reduction.
 void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
@@ -269,6 +270,16 @@ void launch_gram_reduce(hipStream_t st, const float* part, int32_t nchunks, int6
 void launch_fill(hipStream_t st, float* p, int64_t n, float v);
 // One pass of the b = 1 specialisation (coordinate descent, Alg. 2) for coordinate blk.
 void launch_icd_pass(ials_ctx* c, int sd, int32_t blk);
+
+// Workgroups of one kernel resident per CU, kept per device: set_lds raises the kernel's
+// dynamic-LDS limit to lds bytes first (the limit is a per-device attribute), then the
+// occupancy for threads-wide workgroups with lds bytes is queried once per device and
+// cached in cache (one static OccCache per kernel instantiation).  fallback if the query fails.
+struct OccCache {
+    static constexpr int kDevices = 64;
+    std::atomic<int> v[kDevices] = {};
+};
+int resident_per_cu(OccCache& cache, const void* kernel, int threads, size_t lds, bool set_lds, int fallback);
 
 // Allocation helper that tracks the context's byte count and budget.
 hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes);

@@ -314,7 +314,7 @@ ials_status create_server(const ials_server_config* cfg, const float* H, ials_se
     SRV_TRY(hipMemsetAsync(s->cnt, 0, sizeof(int32_t) * ials::FOLD_CNT_NUM, s->streams[0]));
     {
         float* part = nullptr;
-        SRV_TRY(hipMalloc((void**)&part, sizeof(float) * ials::gram_part_floats_needed(f.I, f.d, f.d)));
+        SRV_TRY(hipMalloc((void**)&part, sizeof(float) * ials::gram_part_floats_needed(f.I, f.d, f.d, false)));
         ials::launch_gramian_raw(s->streams[0], H, f.I, f.d, 0, f.d, f.d, part, s->G, false);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(s->streams[0]);

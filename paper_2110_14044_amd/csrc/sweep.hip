@@ -985,15 +985,9 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
             ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
             if (args.rows_batch == 0) {
                 // static dealing: exactly the blocks that are resident at once
-                static int resident = 0;
-                if (resident == 0) {
-                    int nb = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_rows<NT, FULL, TRANS, true, BF>, 256,
-                                                                     lds) != hipSuccess ||
-                        nb < 1)
-                        nb = 2;
-                    resident = nb;
-                }
+                static OccCache occ;
+                const int resident = resident_per_cu(
+                    occ, reinterpret_cast<const void*>(&k_sweep_rows<NT, FULL, TRANS, true, BF>), 256, lds, false, 2);
                 hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true, BF>),
                                    dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
                                    dim3(256), lds, st, args);
@@ -1058,18 +1052,11 @@ void launch_w8_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd
         {
             ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
             // static dealing over exactly the workgroups that are resident at once
-            static std::atomic<int> resident{0};
-            if (resident.load() == 0) {
-                (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows_w8<FULL, TRANS, BF>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                int nb = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rows_w8<FULL, TRANS, BF>, 256, lds) != hipSuccess ||
-                    nb < 1)
-                    nb = 1;
-                resident.store(nb);
-            }
+            static OccCache occ;
+            const int resident =
+                resident_per_cu(occ, reinterpret_cast<const void*>(&k_rows_w8<FULL, TRANS, BF>), 256, lds, true, 1);
             hipLaunchKernelGGL((k_rows_w8<FULL, TRANS, BF>),
-                               dim3(std::min<unsigned>((unsigned)(c->num_cu * resident.load()), (s.nrows + 3) / 4)),
+                               dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
                                dim3(256), lds, st, args);
         }
         ProfScope ps(c, IALS_K_FALLBACK_USER + sd);

@@ -667,17 +667,9 @@ void launch_big_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int s
     }
     if (s.nrows > 0) {
         const size_t lds = sizeof(float) * L::TOTAL;
-        static int resident = 0;
-        if (resident == 0) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows_big<NT, TRANS, BF>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rows_big<NT, TRANS, BF>, (int)threads, lds) !=
-                    hipSuccess ||
-                nb < 1)
-                nb = 1;
-            resident = nb;
-        }
+        static OccCache occ;
+        const int resident = resident_per_cu(occ, reinterpret_cast<const void*>(&k_rows_big<NT, TRANS, BF>),
+                                             (int)threads, lds, true, 1);
         {
             ProfScope ps(c, (TRANS ? IALS_K_ROWS_USER_MOVE : IALS_K_ROWS_USER) + sd);
             hipLaunchKernelGGL((k_rows_big<NT, TRANS, BF>),

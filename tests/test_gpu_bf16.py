@@ -92,6 +92,36 @@ def test_bf16_gramian_at_the_d1024_shape():
     assert e < 1e-2 and eb < 1e-2
 
 
+def _bf16_round(x):
+    """float32 -> bfloat16 (round to nearest even) -> float64, for finite x."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("users,d", [(1000, 256), (20_011, 512)])
+def test_bf16_full_gramian_tiles(users, d):
+    """The full Gramian in 256 x 256 lower tiles (d a multiple of 256): against X_b^T X_b in
+    float64, X_b the table rounded to bfloat16 the way the kernel rounds it, so that only the
+    float32 accumulation separates the two (bar 1e-5 relative, element-wise against the largest
+    magnitude of the row and column); ragged row chunks, empty chunks and off-diagonal tiles
+    included.  G must be exactly symmetric and the same on a second call."""
+    p = synth.small_problem(240 + d, users, 300, 6 * users, d, 64, std=0.1)
+    tr = gpu_trainer(p, precision=BF16)
+    G = host(tr.gramian(0, -1))
+    G2 = host(tr.gramian(0, -1))
+    tr.close()
+    Xb = _bf16_round(p.W0)
+    ref = Xb.T @ Xb
+    scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+    e = float(np.max(np.abs(G - ref) / scale))
+    say(f"bf16 full Gramian {users} x {d}: max element error {e:.2e} of sqrt(G_ff G_qq); "
+        f"vs float64 of the float32 table {rel(G, oracle.gramian(p.W0)):.2e}")
+    assert np.array_equal(G, G.T)
+    assert np.array_equal(G, G2)
+    assert e < 1e-5
+
+
 def test_bf16_bitwise_deterministic():
     p = synth.small_problem(230, 2000, 100, 40_000, 64, 32, zipf_s=0.9, std=0.1)
     outs = []
