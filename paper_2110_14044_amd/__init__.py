@@ -18,14 +18,19 @@ class Trainer:
 
     def __init__(self, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
                  stream=None, device: str = "cuda", hbm_budget: int = 0, graph: bool = False, deal: str = "auto",
-                 seg_len: int = 0):
+                 seg_len: int = 0, W0=None, H0=None):
         import numpy as np
         import torch
 
         binding.load()
         self.problem = problem
-        self.W = torch.from_numpy(np.ascontiguousarray(problem.W0)).to(device)
-        self.H = torch.from_numpy(np.ascontiguousarray(problem.H0)).to(device)
+        self.config = {"num_users": problem.num_users, "num_items": problem.num_items, "dim": problem.dim,
+                       "block": problem.block, "alpha0": float(problem.alpha0), "lam": float(problem.lam),
+                       "precision": int(precision), "chol_fallback_ratio": float(chol_fallback_ratio),
+                       "deal": deal, "seg_len": int(seg_len)}
+        self.epochs_done = 0
+        self.W = torch.from_numpy(np.ascontiguousarray(problem.W0 if W0 is None else W0)).to(device)
+        self.H = torch.from_numpy(np.ascontiguousarray(problem.H0 if H0 is None else H0)).to(device)
         if stream is None:
             stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
         self.stream = stream
@@ -45,6 +50,77 @@ class Trainer:
 
     def epoch(self, n: int = 1):
         binding.ials_epoch(self.ctx, n)
+        self.epochs_done += n
+
+    def save_checkpoint(self, path: str):
+        """W, H, the epochs done and the configuration at this epoch boundary (see checkpoint)."""
+        from . import checkpoint
+        self.synchronize()
+        checkpoint.save(path, self.W.cpu().numpy(), self.H.cpu().numpy(), self.epochs_done, self.config,
+                        checkpoint.data_fingerprint(self.problem))
+
+    @classmethod
+    def resume(cls, path: str, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
+               deal: str = "auto", seg_len: int = 0, **kw):
+        """A trainer that continues the run saved in `path` on the same observations and configuration
+        (checked: ValueError otherwise); on the same device it repeats the uninterrupted run bit for bit."""
+        from . import checkpoint
+        config = {"num_users": problem.num_users, "num_items": problem.num_items, "dim": problem.dim,
+                  "block": problem.block, "alpha0": float(problem.alpha0), "lam": float(problem.lam),
+                  "precision": int(precision), "chol_fallback_ratio": float(chol_fallback_ratio), "deal": deal,
+                  "seg_len": int(seg_len)}
+        W, H, meta = checkpoint.load(path, config, checkpoint.data_fingerprint(problem))
+        tr = cls(problem, precision=precision, chol_fallback_ratio=chol_fallback_ratio, deal=deal, seg_len=seg_len,
+                 W0=W, H0=H, **kw)
+        tr.epochs_done = meta["epochs_done"]
+        return tr
+
+    def fit(self, epochs: int, metrics_path: str | None = None, profile: bool = False, extra=None,
+            checkpoint_path: str | None = None, checkpoint_every: int = 0, with_loss: bool = True):
+        """Run `epochs` epochs one at a time; after each, append one JSON record to `metrics_path`
+        (if given) and return the records: epoch index, loss (float64, eq. 2; skipped without
+        with_loss, as it recomputes every prediction), epoch_s (HIP events
+        on the context's stream), nnz*b/s (2 |S| d per epoch), the rows redone in float64 during the
+        epoch, per-kernel-family milliseconds and launches when `profile`, and whatever
+        extra(trainer, epoch) returns.  With checkpoint_path and checkpoint_every = k, a checkpoint
+        is written after every k-th epoch."""
+        import json
+        import torch
+        from . import checkpoint
+        records = []
+        if profile:
+            binding.ials_profile_enable(self.ctx, True)
+        fb0 = self.stats()["fallback_rows"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(epochs):
+            e0.record(self.stream)
+            self.epoch(1)
+            e1.record(self.stream)
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            kern = checkpoint.kernel_record(binding.ials_profile_read(self.ctx)) if profile else None
+            st = self.stats()
+            rec = {"epoch": self.epochs_done, "epoch_s": sec,
+                   "nnz_b_per_s": 2.0 * self.problem.nnz * self.problem.dim / sec,
+                   "fallback_rows": st["fallback_rows"] - fb0}
+            fb0 = st["fallback_rows"]
+            if with_loss:
+                L, parts = self.loss()
+                rec["loss"], rec["loss_parts"] = L, list(parts)
+            if profile:
+                rec["kernels"] = kern
+                binding.ials_profile_read(self.ctx)  # drop the loss evaluation's launches
+            if extra is not None:
+                rec.update(extra(self, self.epochs_done))
+            records.append(rec)
+            if metrics_path:
+                with open(metrics_path, "a") as f:
+                    f.write(json.dumps(rec) + "\n")
+            if checkpoint_path and checkpoint_every and self.epochs_done % checkpoint_every == 0:
+                self.save_checkpoint(checkpoint_path)
+        if profile:
+            binding.ials_profile_enable(self.ctx, False)
+        return records
 
     def synchronize(self):
         self.stream.synchronize()

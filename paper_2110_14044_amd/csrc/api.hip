@@ -232,7 +232,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->B = cfg->block <= 64 ? (cfg->block + 15) / 16 * 16 : (cfg->block <= 128 ? 128 : 256);
     c->alpha0 = cfg->alpha0;
     c->lambda = cfg->lambda;
-    c->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-4f;
+    c->tau = ials::effective_tau(cfg->chol_fallback_ratio);
     c->precision = cfg->precision;
     c->seg_len = cfg->seg_len ? (int32_t)cfg->seg_len : ials::kSegLenDefault;
     c->nnz = S->nnz;

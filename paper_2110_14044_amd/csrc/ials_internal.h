@@ -287,6 +287,13 @@ hipError_t dev_alloc(ials_ctx* c, void** p, size_t bytes);
 // (device_bytes + tmp_bytes never exceeds it), released by tmp_free.
 hipError_t tmp_alloc(ials_ctx* c, void** p, size_t bytes);
 void tmp_free(ials_ctx* c, void* p, size_t bytes);
+// The pivot threshold the kernels compare with (min pivot < tau * largest diagonal entry):
+// <= 0 selects 1e-4; >= 1 becomes the largest float, so that every row fails the test (with
+// tau = 1 a row whose pivots all equal its largest diagonal entry would pass).
+inline float effective_tau(float ratio) {
+    if (!(ratio > 0.f)) return 1e-4f;
+    return ratio >= 1.f ? 3.4e38f : ratio;
+}
 // IALS_E_NOMEM for an allocation failure or an exceeded budget, IALS_E_HIP otherwise.
 inline ials_status alloc_status(hipError_t e) { return e == hipErrorOutOfMemory ? IALS_E_NOMEM : IALS_E_HIP; }
 

@@ -287,7 +287,7 @@ ials_status create_server(const ials_server_config* cfg, const float* H, ials_se
     s->fold = f;
     s->alpha0 = cfg->alpha0;
     s->lambda = cfg->lambda;
-    s->tau = cfg->chol_fallback_ratio > 0.f ? cfg->chol_fallback_ratio : 1e-4f;
+    s->tau = ials::effective_tau(cfg->chol_fallback_ratio);
     s->passes = cfg->passes;
     s->max_slots = cfg->max_slots;
     s->nstreams = cfg->streams ? cfg->streams : 4;
