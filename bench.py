@@ -116,16 +116,17 @@ def traffic_file(kernel_family, workload):
     return os.path.join(ROOT, "profiles", f"traffic_{kernel_family}_{workload}.txt")
 
 
-def measured_traffic(kernel_family, workload, block, precision):
+def measured_traffic(kernel_family, workload, block, precision, seg_len=SEG_LEN):
     """HBM bytes per launch of a kernel family from the committed counter summary, or None if
-    there is none for this workload, block and precision, or if the kernel's source changed
-    since the counters were taken (its hash is stored beside the figures)."""
+    there is none for this workload, block, precision and segment length (which decides the rows
+    the kernel takes), or if the kernel's source changed since the counters were taken (its hash
+    is stored beside the figures)."""
     path = traffic_file(kernel_family, workload)
     if not os.path.exists(path):
         return None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    if (kv.get("kernel"), kv.get("workload"), kv.get("block"), kv.get("precision")) != (
-            kernel_family, workload, str(block), precision):
+    if (kv.get("kernel"), kv.get("workload"), kv.get("block"), kv.get("precision"), kv.get("seg_len")) != (
+            kernel_family, workload, str(block), precision, str(seg_len)):
         return None
     src = os.path.join(ROOT, "paper_2110_14044_amd", "csrc", kv.get("source", "sweep.hip"))
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
@@ -297,14 +298,14 @@ def kernel_table(prof, steps):
             for name, (ms, cnt) in prof.items() if cnt > 0}
 
 
-def train_leg(p, prec_name, steps, warmup, deal="auto", seg_len=0, graph=True, prof_steps=None):
+def train_leg(p, prec_name, steps, warmup, deal="auto", seg_len=0, graph=True, prof_steps=None, gram_split=0):
     """Warm-up epochs, then `steps` epochs timed together (replayed from the epoch graph), then
     `prof_steps` epochs launched kernel by kernel with HIP events around every kernel."""
     import torch
     from paper_2110_14044_amd import Trainer, binding
     prec = binding.IALS_PREC_BF16 if prec_name == "bf16" else binding.IALS_PREC_FP32
     prof_steps = steps if prof_steps is None else prof_steps
-    tr = Trainer(p, graph=graph, precision=prec, deal=deal, seg_len=seg_len)
+    tr = Trainer(p, graph=graph, precision=prec, deal=deal, seg_len=seg_len, gram_split=gram_split)
     torch.cuda.synchronize()
     st = tr.stats()
     log(f"[bench] {p.name} b={p.block} {prec_name}: index built, long rows user {st['long_rows_user']} item "
@@ -376,7 +377,7 @@ def rooflines(p, prec_name, kern, seg_len, epoch_s):
         "kernel": row_kernel_name(dom, p, prec_name) + ": gather + MFMA Hessian + blocked LDL^T solve + update",
         "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
         "frac": round(achieved / peak, 4),
-        "traffic": measured_traffic(dom, p.name, p.block, prec_name),
+        "traffic": measured_traffic(dom, p.name, p.block, prec_name, seg),
         "peak_basis": f"{prec_name} operands on the matrix cores" if bound == "mfma" else "HBM3E",
         "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_,
         "avg_launch_ms": kern[dom]["avg_ms"], "algorithmic_TFLOPs": round(flops / avg_s / 1e12, 2),
@@ -476,7 +477,7 @@ def cpu_baseline_sampled(p, frac=0.05, seed=7):
             "sample": sample, "seconds": t5 - t0, "epoch_s_estimate": est}
 
 
-def matched_loss(p, epochs, deal="auto", seg_len=0):
+def matched_loss(p, epochs, deal="auto", seg_len=0, gram_split=0):
     """Plain float32 form against the bfloat16 form on the same workload at the same b.  Each form
     runs `epochs` epochs from W0, H0; L* is the float32 form's loss after the last one.  Each form
     is charged the time of its epochs up to the first whose loss is within L*(1 + 1e-3) (the same
@@ -488,10 +489,10 @@ def matched_loss(p, epochs, deal="auto", seg_len=0):
     from paper_2110_14044_amd import Trainer, binding
     out = {}
     for name, prec in (("fp32", binding.IALS_PREC_FP32), ("bf16", binding.IALS_PREC_BF16)):
-        warm = Trainer(p, precision=prec, deal=deal, seg_len=seg_len)
+        warm = Trainer(p, precision=prec, deal=deal, seg_len=seg_len, gram_split=gram_split)
         warm.epoch(1)
         warm.close()
-        tr = Trainer(p, precision=prec, deal=deal, seg_len=seg_len)
+        tr = Trainer(p, precision=prec, deal=deal, seg_len=seg_len, gram_split=gram_split)
         times, losses = [], []
         for t in range(epochs):
             torch.cuda.synchronize()
@@ -620,6 +621,8 @@ def main():
     ap.add_argument("--seg-len", type=int, default=0,
                     help="observations per segment of long rows (0: the library default, 512)")
     ap.add_argument("--deal", choices=("auto", "static", "queue"), default="auto", help="row dealing of the row kernels")
+    ap.add_argument("--gram-split", type=int, default=0,
+                    help="workgroups the Gramian slab's split-K is sized for (0: the library's 512 or the autotuner's)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: the autotuner's own)")
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
                     help="arithmetic of the headline epochs (bf16: bfloat16 Hessian and Gramian products)")
@@ -684,7 +687,7 @@ def main():
     t0 = time.time()
     p = synth.make_problem(args.workload)
     log(f"[bench] generated in {time.time() - t0:.1f}s")
-    deal, seg_len, tuned = args.deal, args.seg_len, None
+    deal, seg_len, gram_split, tuned = args.deal, args.seg_len, args.gram_split, None
     if args.block:
         p.block = args.block
     elif not args.no_autotune:
@@ -692,12 +695,14 @@ def main():
         prec = binding.IALS_PREC_BF16 if args.precision == "bf16" else binding.IALS_PREC_FP32
         t0 = time.time()
         tuned = autotune.tune(p, prec, cache_path=args.tune_cache, log=log)
-        p.block, deal, seg_len = tuned["block"], tuned["deal"], tuned["seg_len"]
+        p.block, deal, seg_len, gram_split = tuned["block"], tuned["deal"], tuned["seg_len"], tuned["gram_split"]
         tuned = {k: v for k, v in tuned.items() if k != "trials"} | {
-            "trials": [{k: t[k] for k in ("block", "deal", "seg_len", "epoch_ms")} for t in tuned["trials"]],
+            "trials": [{k: t[k] for k in ("block", "deal", "seg_len", "gram_split", "epoch_ms")}
+                       for t in tuned["trials"]],
             "tune_s": round(time.time() - t0, 1)}
-        log(f"[bench] tuned: b={p.block} deal={deal} seg_len={seg_len} (estimated epoch {tuned['epoch_ms']:.1f} ms)")
-    leg = train_leg(p, args.precision, args.steps, args.warmup, deal=deal, seg_len=seg_len,
+        log(f"[bench] tuned: b={p.block} deal={deal} seg_len={seg_len} gram_split={gram_split} "
+            f"(estimated epoch {tuned['epoch_ms']:.1f} ms)")
+    leg = train_leg(p, args.precision, args.steps, args.warmup, deal=deal, seg_len=seg_len, gram_split=gram_split,
                     graph=not args.no_graph)
     leg.pop("trainer").close()
     epoch_s = leg["epoch_s"]
@@ -707,7 +712,7 @@ def main():
     matched = None
     if args.matched_loss_epochs > 0 and args.precision == "fp32":
         log(f"[bench] {p.name}: float32 vs bfloat16 at matched loss, {args.steps} epochs")
-        matched = matched_loss(p, args.steps, deal=deal, seg_len=seg_len)
+        matched = matched_loss(p, args.steps, deal=deal, seg_len=seg_len, gram_split=gram_split)
         for k in ("fp32", "bf16"):
             for drop in ("kernels", "kernel_rates"):
                 matched[k].pop(drop, None)
@@ -738,6 +743,7 @@ def main():
                                f"({'autotuned over 32/64/128/256' if tuned else 'fixed'}), alpha0={wl.alpha0}, "
                                f"lambda={wl.lam}, {args.precision} arithmetic",
                    "epoch_s": epoch_s, "parallelism": "single GPU", "deal": deal, "seg_len": seg_len or SEG_LEN,
+                   "gram_split": gram_split or 512,
                    "graph": not args.no_graph},
         "autotune": tuned,
         "epoch_s": epoch_s, "loss_after": leg["loss_after"], "epochs_trained": leg["epochs_trained"],

@@ -105,6 +105,12 @@ typedef struct {
                                    0 selects 512 */
     uint64_t hbm_budget;        /* upper bound on the library's device bytes held at any time,
                                    the temporaries of ials_create included; 0 = no bound */
+    uint32_t gram_split;        /* split-K of the per-pass Gramian slab (eq. 7): the number of
+                                   workgroups its row chunks and output tiles are sized for, a
+                                   power of two in [64, 2048]; 0 selects 512.  The chunk partials
+                                   are added in float64 in chunk order, so a different split
+                                   rounds differently (results stay deterministic per split) */
+    uint32_t reserved;          /* 0 */
 } ials_config;
 
 typedef struct {

@@ -18,7 +18,7 @@ class Trainer:
 
     def __init__(self, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
                  stream=None, device: str = "cuda", hbm_budget: int = 0, graph: bool = False, deal: str = "auto",
-                 seg_len: int = 0, W0=None, H0=None):
+                 seg_len: int = 0, W0=None, H0=None, gram_split: int = 0):
         import numpy as np
         import torch
 
@@ -27,7 +27,7 @@ class Trainer:
         self.config = {"num_users": problem.num_users, "num_items": problem.num_items, "dim": problem.dim,
                        "block": problem.block, "alpha0": float(problem.alpha0), "lam": float(problem.lam),
                        "precision": int(precision), "chol_fallback_ratio": float(chol_fallback_ratio),
-                       "deal": deal, "seg_len": int(seg_len)}
+                       "deal": deal, "seg_len": int(seg_len), "gram_split": int(gram_split)}
         self.epochs_done = 0
         self.W = torch.from_numpy(np.ascontiguousarray(problem.W0 if W0 is None else W0)).to(device)
         self.H = torch.from_numpy(np.ascontiguousarray(problem.H0 if H0 is None else H0)).to(device)
@@ -38,7 +38,7 @@ class Trainer:
                                                              "static": binding.IALS_FLAG_DEAL_STATIC}[deal]
         cfg = binding.make_config(problem.num_users, problem.num_items, problem.dim, problem.block,
                                   problem.alpha0, problem.lam, precision, chol_fallback_ratio, hbm_budget, flags,
-                                  seg_len)
+                                  seg_len, gram_split)
         u = np.ascontiguousarray(problem.user, np.int32)
         i = np.ascontiguousarray(problem.item, np.int32)
         y = None if problem.y is None else np.ascontiguousarray(problem.y, np.float32)
@@ -61,17 +61,17 @@ class Trainer:
 
     @classmethod
     def resume(cls, path: str, problem, precision: int = binding.IALS_PREC_FP32, chol_fallback_ratio: float = 0.0,
-               deal: str = "auto", seg_len: int = 0, **kw):
+               deal: str = "auto", seg_len: int = 0, gram_split: int = 0, **kw):
         """A trainer that continues the run saved in `path` on the same observations and configuration
         (checked: ValueError otherwise); on the same device it repeats the uninterrupted run bit for bit."""
         from . import checkpoint
         config = {"num_users": problem.num_users, "num_items": problem.num_items, "dim": problem.dim,
                   "block": problem.block, "alpha0": float(problem.alpha0), "lam": float(problem.lam),
                   "precision": int(precision), "chol_fallback_ratio": float(chol_fallback_ratio), "deal": deal,
-                  "seg_len": int(seg_len)}
+                  "seg_len": int(seg_len), "gram_split": int(gram_split)}
         W, H, meta = checkpoint.load(path, config, checkpoint.data_fingerprint(problem))
         tr = cls(problem, precision=precision, chol_fallback_ratio=chol_fallback_ratio, deal=deal, seg_len=seg_len,
-                 W0=W, H0=H, **kw)
+                 gram_split=gram_split, W0=W, H0=H, **kw)
         tr.epochs_done = meta["epochs_done"]
         return tr
 

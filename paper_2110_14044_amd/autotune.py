@@ -13,8 +13,9 @@ hooks, and estimates the epoch as
     predictions + (user pass + item pass) of the first block
                 + (nb - 1) x (user pass that moves the prediction cache + item pass)
 
-Then, at the best b, it tries the other row dealing and two other segment
-lengths.  A different b is a different trajectory of the iteration (the blocks
+Then, at the best b, it tries the other row dealing, the other segment lengths
+(the split-K of long rows) and the split-K of the per-pass Gramian slab (how many
+workgroups its row chunks are sized for).  A different b is a different trajectory of the iteration (the blocks
 are different coordinate subspaces), so results must be checked against the
 oracle at the chosen b.  Results are cached in a JSON file keyed by the problem
 shape, the arithmetic and the device.
@@ -32,6 +33,8 @@ CANDIDATE_B = (32, 64, 128, 256)
 SEG_LENS = (256, 512, 1024, 2048)
 DEFAULT_SEG_LEN = 512  # the library's segment length when ials_config.seg_len is 0
 DEALS = ("static", "queue")
+GRAM_SPLITS = (256, 512, 1024, 2048)
+DEFAULT_GRAM_SPLIT = 512  # the library's Gramian split when ials_config.gram_split is 0
 
 
 def default_cache_path() -> str:
@@ -68,13 +71,13 @@ def _predict_ms(tr) -> float:
 
 
 def estimate_epoch_ms(problem, block: int, precision: int = binding.IALS_PREC_FP32, deal: str = "auto",
-                      seg_len: int = 0, repeats: int = 2) -> dict:
+                      seg_len: int = 0, gram_split: int = 0, repeats: int = 2) -> dict:
     """Build a context for `problem` at block size `block` and estimate its epoch time from timed passes."""
     from . import Trainer
     q = copy.copy(problem)
     q.block = block
     nb = math.ceil(q.dim / block)
-    tr = Trainer(q, precision=precision, deal=deal, seg_len=seg_len)
+    tr = Trainer(q, precision=precision, deal=deal, seg_len=seg_len, gram_split=gram_split)
     try:
         # load every kernel once (the first pass of a new block moves the prediction cache)
         tr.block_sweep(0, 0)
@@ -96,17 +99,22 @@ def estimate_epoch_ms(problem, block: int, precision: int = binding.IALS_PREC_FP
                    "user_move_ms": move_user, "item_ms": item}
             if best is None or cur["epoch_ms"] < best["epoch_ms"]:
                 best = cur
-        best.update({"block": block, "nblocks": nb, "deal": deal, "seg_len": seg_len or DEFAULT_SEG_LEN})
+        best.update({"block": block, "nblocks": nb, "deal": deal, "seg_len": seg_len or DEFAULT_SEG_LEN,
+                     "gram_split": gram_split or DEFAULT_GRAM_SPLIT})
         return best
     finally:
         tr.close()
 
 
 def tune(problem, precision: int = binding.IALS_PREC_FP32, candidates=CANDIDATE_B, cache_path: str | None = None,
-         refresh: bool = False, log=None) -> dict:
-    """Choose b (then row dealing and segment length at that b) for `problem` by measurement.
+         refresh: bool = False, log=None, min_gain: float = 0.01) -> dict:
+    """Choose b (then row dealing, segment length and Gramian split at that b) for `problem` by
+    measurement.  b takes the fastest candidate; the later settings replace the library's default
+    only when they are faster by more than `min_gain` (a fraction of the estimated epoch), so that
+    run-to-run timing noise does not flip the choice.
 
-    Returns {"block", "deal", "seg_len", "epoch_ms", "trials": [...]} and stores it in the cache."""
+    Returns {"block", "deal", "seg_len", "gram_split", "epoch_ms", "trials": [...]} and stores it in the
+    cache."""
     import torch
     cache_path = cache_path or default_cache_path()
     key = problem_key(problem, precision)
@@ -114,7 +122,7 @@ def tune(problem, precision: int = binding.IALS_PREC_FP32, candidates=CANDIDATE_
     if os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
-    if key in cache and not refresh:
+    if key in cache and not refresh and "gram_split" in cache[key]:
         return cache[key]
     say = log or (lambda *a: None)
     trials = []
@@ -131,7 +139,7 @@ def tune(problem, precision: int = binding.IALS_PREC_FP32, candidates=CANDIDATE_
         r = estimate_epoch_ms(problem, best["block"], precision, deal=deal)
         trials.append(r)
         say(f"[tune] b={best['block']} deal={deal}: epoch {r['epoch_ms']:.1f} ms")
-        if r["epoch_ms"] < best["epoch_ms"]:
+        if r["epoch_ms"] < best["epoch_ms"] * (1.0 - min_gain):
             best = r
     for seg in SEG_LENS:
         if seg == DEFAULT_SEG_LEN:
@@ -139,9 +147,20 @@ def tune(problem, precision: int = binding.IALS_PREC_FP32, candidates=CANDIDATE_
         r = estimate_epoch_ms(problem, best["block"], precision, deal=best["deal"], seg_len=seg)
         trials.append(r)
         say(f"[tune] b={best['block']} deal={best['deal']} seg_len={seg}: epoch {r['epoch_ms']:.1f} ms")
-        if r["epoch_ms"] < best["epoch_ms"]:
+        if r["epoch_ms"] < best["epoch_ms"] * (1.0 - min_gain):
             best = r
-    out = {"block": best["block"], "deal": best["deal"], "seg_len": best["seg_len"], "epoch_ms": best["epoch_ms"],
+    for split in GRAM_SPLITS:
+        if split == DEFAULT_GRAM_SPLIT:
+            continue
+        r = estimate_epoch_ms(problem, best["block"], precision, deal=best["deal"], seg_len=best["seg_len"],
+                              gram_split=split)
+        trials.append(r)
+        say(f"[tune] b={best['block']} deal={best['deal']} seg_len={best['seg_len']} gram_split={split}: "
+            f"epoch {r['epoch_ms']:.1f} ms")
+        if r["epoch_ms"] < best["epoch_ms"] * (1.0 - min_gain):
+            best = r
+    out = {"block": best["block"], "deal": best["deal"], "seg_len": best["seg_len"],
+           "gram_split": best["gram_split"], "epoch_ms": best["epoch_ms"],
            "key": key, "trials": trials}
     cache[key] = out
     os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

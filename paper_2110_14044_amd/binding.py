@@ -48,7 +48,8 @@ class ials_config(C.Structure):
     _fields_ = [("num_users", C.c_int32), ("num_items", C.c_int32), ("dim", C.c_int32),
                 ("block", C.c_int32), ("alpha0", C.c_float), ("lambda_", C.c_float),
                 ("precision", C.c_int32), ("chol_fallback_ratio", C.c_float), ("flags", C.c_uint32),
-                ("seg_len", C.c_uint32), ("hbm_budget", C.c_uint64)]
+                ("seg_len", C.c_uint32), ("hbm_budget", C.c_uint64), ("gram_split", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class ials_coo(C.Structure):
@@ -333,9 +334,9 @@ def ials_version() -> str:
 
 
 def make_config(num_users, num_items, dim, block, alpha0, lam, precision=IALS_PREC_FP32,
-                chol_fallback_ratio=0.0, hbm_budget=0, flags=0, seg_len=0) -> ials_config:
+                chol_fallback_ratio=0.0, hbm_budget=0, flags=0, seg_len=0, gram_split=0) -> ials_config:
     return ials_config(num_users, num_items, dim, block, alpha0, lam, precision, chol_fallback_ratio, flags, seg_len,
-                       hbm_budget)
+                       hbm_budget, gram_split, 0)
 
 
 def make_coo(user, item, y=None, alpha=None, memkind=IALS_MEM_HOST) -> ials_coo:

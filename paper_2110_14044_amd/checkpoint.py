@@ -20,7 +20,7 @@ import numpy as np
 FORMAT = "ials-checkpoint-1"
 # configuration fields a resumed run must share with the saved one
 CONFIG_KEYS = ("num_users", "num_items", "dim", "block", "alpha0", "lam", "precision", "chol_fallback_ratio",
-               "deal", "seg_len")
+               "deal", "seg_len", "gram_split")
 
 
 def data_fingerprint(problem) -> str:

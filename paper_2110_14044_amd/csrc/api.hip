@@ -203,6 +203,11 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
         g_create_error = "unknown or conflicting flag bits";
         return IALS_E_INVALID;
     }
+    if (cfg->gram_split != 0 && (cfg->gram_split < 64 || cfg->gram_split > 2048 ||
+                                 (cfg->gram_split & (cfg->gram_split - 1)) != 0)) {
+        g_create_error = "gram_split must be 0 or a power of two in [64, 2048]";
+        return IALS_E_INVALID;
+    }
     if (cfg->seg_len != 0 && (cfg->seg_len % 64 != 0 || cfg->seg_len < 256 || cfg->seg_len > 65536)) {
         g_create_error = "seg_len must be 0 or a multiple of 64 in [256, 65536]";
         return IALS_E_INVALID;
@@ -235,6 +240,7 @@ ials_status create_impl(const ials_config* cfg, const ials_coo* S, float* W, flo
     c->tau = ials::effective_tau(cfg->chol_fallback_ratio);
     c->precision = cfg->precision;
     c->seg_len = cfg->seg_len ? (int32_t)cfg->seg_len : ials::kSegLenDefault;
+    c->gram_split = cfg->gram_split ? (int32_t)cfg->gram_split : ials::kGramSplitDefault;
     c->nnz = S->nnz;
     c->stream = (hipStream_t)stream;
     c->W = W;

@@ -1001,7 +1001,7 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
 
 // out (d x ncols) = X^T X[:, p0:p0+bw] (zero columns for q >= bw).
 void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
-                        float* part, float* out, bool bf16) {
+                        float* part, float* out, bool bf16, int32_t split) {
     const int64_t ft = (d + 63) / 64;
     const int qt16 = (ncols + 15) / 16;
     const int QT = qt16 >= 4 ? 4 : (qt16 >= 2 ? 2 : 1);
@@ -1027,7 +1027,7 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
     if (d % 64 == 0 && ncols % 64 == 0 && bw == ncols && p0 % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
         // full 64 x 64 tiles with 16-byte loads; four wavefronts per block, so a quarter of the
         // blocks (and of the partials the reduction reads) for the same number of wavefronts
-        const int rv = chunk_rows_for(n, ft * qg, 512, 256);
+        const int rv = chunk_rows_for(n, ft * qg, split, 256);
         const int64_t cv = std::max<int64_t>(1, (n + rv - 1) / rv);
         if (bf16)
             hipLaunchKernelGGL(k_gram_vec_bf16, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d,
@@ -1058,7 +1058,8 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
 // the pass and resets the sweep cursors.
 void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw, int32_t ncols, float* out,
                          bool make_dmat) {
-    launch_gramian_raw(c->stream, X, n, c->d, p0, bw, ncols, c->gram_part, out, c->precision == IALS_PREC_BF16);
+    launch_gramian_raw(c->stream, X, n, c->d, p0, bw, ncols, c->gram_part, out, c->precision == IALS_PREC_BF16,
+                       c->gram_split);
     if (make_dmat)
         hipLaunchKernelGGL(k_make_dmat, dim3(nblk(std::max(c->B * c->B, (int)CUR_NUM), 256)), dim3(256), 0, c->stream,
                            out, c->B, p0, bw, c->alpha0, c->lambda, c->Dmat, c->cursors);

@@ -32,6 +32,7 @@ __device__ inline float row_sum16(float s) {
 // segments of that many observations, each accumulated by its own wavefront (or
 // workgroup), then reduced in a fixed order.
 constexpr int kSegLenDefault = 512;
+constexpr int kGramSplitDefault = 512;
 
 // Device-side counters/flags block (int64), zeroed at create.
 enum Counter : int {
@@ -127,6 +128,7 @@ struct ials_ctx {
     float alpha0 = 0.f, lambda = 0.f, tau = 1e-4f;
     int32_t precision = 0;
     int32_t seg_len = ials::kSegLenDefault;
+    int32_t gram_split = ials::kGramSplitDefault;  // workgroups the Gramian slab's split-K is sized for
     int64_t nnz = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -250,8 +252,9 @@ ials_status launch_loss(ials_ctx* c);
 size_t gram_part_floats_needed(int32_t n, int32_t d, int32_t ncols, bool bf16);
 // out (d x ncols) = X^T X[:, p0:p0+bw] with the split-K partials in part (gram_part_floats_needed floats);
 // bf16: bfloat16 operands on the matrix cores, float32 partials, float64 reduction.
+// split: workgroups the split-K of the 64 x 64-tile kernels is sized for (64..2048).
 void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, int32_t p0, int32_t bw, int32_t ncols,
-                        float* part, float* out, bool bf16);
+                        float* part, float* out, bool bf16, int32_t split = kGramSplitDefault);
 FoldShape fold_shape(int32_t I, int32_t d, int32_t b);
 size_t fold_ws_floats(const FoldShape& f, int64_t n);
 // Fold-in of m requests (one workgroup each) against H (I x d) and G = H^T H (d x d).

@@ -47,7 +47,10 @@ def test_create_rejects_bad_config_before_device_work(lib):
     S = binding.ials_coo(0, None, None, None, None, 0, 0)
     for cfg in [binding.make_config(0, 10, 16, 8, 0.1, 0.1), binding.make_config(10, 10, 16, 0, 0.1, 0.1),
                 binding.make_config(10, 10, 16, 32, 0.1, 0.1), binding.make_config(10, 10, 16, 8, 0.1, 0.0),
-                binding.make_config(10, 10, 512, 257, 0.1, 0.1), binding.make_config(10, 10, 16, 8, -1.0, 0.1)]:
+                binding.make_config(10, 10, 512, 257, 0.1, 0.1), binding.make_config(10, 10, 16, 8, -1.0, 0.1),
+                binding.make_config(10, 10, 16, 8, 0.1, 0.1, gram_split=100),
+                binding.make_config(10, 10, 16, 8, 0.1, 0.1, gram_split=32),
+                binding.make_config(10, 10, 16, 8, 0.1, 0.1, gram_split=4096)]:
         out = C.c_void_p()
         st = lib.ials_create(C.byref(cfg), C.byref(S), 1, 1, None, C.byref(out))
         assert st == binding.IALS_E_INVALID

@@ -14,7 +14,7 @@ from paper_2110_14044_amd import checkpoint
 from tests.gpu_util import oracle_setup
 
 CFG = dict(num_users=0, num_items=0, dim=0, block=0, alpha0=0.1, lam=0.1, precision=0, chol_fallback_ratio=0.0,
-           deal="auto", seg_len=0)
+           deal="auto", seg_len=0, gram_split=0)
 
 
 def _cfg(p, **kw):

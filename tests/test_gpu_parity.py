@@ -220,6 +220,13 @@ def test_long_rows_in_segment_groups(b):
     assert st["segments_item"] > 0 and st["long_rows_item"] > 0
 
 
+@pytest.mark.parametrize("split", [64, 2048])
+def test_gramian_split_extremes(split):
+    # the per-pass Gramian slab with its row chunks sized for 64 and for 2,048 workgroups
+    p = synth.small_problem(58, 20_000, 3000, 200_000, 128, 64, labels=True, zipf_s=0.9, std=0.1)
+    _epoch_check(p, 1, 1e-4, 1e-6, gram_split=split)
+
+
 def test_forced_float64_fallback_matches():
     p = synth.make_problem("tiny")
     st = _epoch_check(p, 1, 1e-4, 1e-6, chol_fallback_ratio=1.0)
