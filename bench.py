@@ -124,14 +124,27 @@ def measured_traffic(kernel_family, workload, block, precision, seg_len=SEG_LEN)
     path = traffic_file(kernel_family, workload)
     if not os.path.exists(path):
         return None
-    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
-    if (kv.get("kernel"), kv.get("workload"), kv.get("block"), kv.get("precision"), kv.get("seg_len")) != (
-            kernel_family, workload, str(block), precision, str(seg_len)):
-        return None
-    src = os.path.join(ROOT, "paper_2110_14044_amd", "csrc", kv.get("source", "sweep.hip"))
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
-        return None
-    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
+    # records of key=value lines, separated by blank lines
+    records, kv = [], {}
+    for line in list(open(path)) + [""]:
+        line = line.strip()
+        if not line:
+            if kv:
+                records.append(kv)
+            kv = {}
+        elif "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k] = v
+    for kv in records:
+        if (kv.get("kernel"), kv.get("workload"), kv.get("block"), kv.get("precision"), kv.get("seg_len")) != (
+                kernel_family, workload, str(block), precision, str(seg_len)):
+            continue
+        src = os.path.join(ROOT, "paper_2110_14044_amd", "csrc", kv.get("source", "sweep.hip"))
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+            return None
+        return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
+    return None
 
 
 def _open_loop(srv, reqs, arrivals, d):

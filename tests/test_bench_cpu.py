@@ -17,14 +17,17 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_and_source(tmp_path, m
     prof.mkdir()
     (prof / "traffic_rows_user_move_msd_like.txt").write_text(
         "# comment\nkernel=rows_user_move\nworkload=msd_like\nblock=64\nprecision=fp32\nseg_len=512\nsource=k.hip\n"
-        f"source_sha256={h}\nfetch_kib=1000\nwrite_kib=100\nfetch_scale=2.0\nwrite_scale=1.0\n")
+        f"source_sha256={h}\nfetch_kib=1000\nwrite_kib=100\nfetch_scale=2.0\nwrite_scale=1.0\n\n"
+        "kernel=rows_user_move\nworkload=msd_like\nblock=64\nprecision=fp32\nseg_len=2048\nsource=k.hip\n"
+        f"source_sha256={h}\nfetch_kib=3000\nwrite_kib=300\nfetch_scale=2.0\nwrite_scale=1.0\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # FETCH_SIZE x 2 + WRITE_SIZE x 1, in KiB
     assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32") == (2000 + 100) * 1024
     assert bench.measured_traffic("rows_user", "msd_like", 64, "fp32") is None
     assert bench.measured_traffic("rows_user_move", "msd_like", 32, "fp32") is None
     assert bench.measured_traffic("rows_user_move", "msd_like", 64, "bf16") is None
-    assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32", 2048) is None
+    assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32", 2048) == (6000 + 300) * 1024
+    assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32", 1024) is None
     assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32", 512) == (2000 + 100) * 1024
     (src / "k.hip").write_text("kernel source, changed\n")
     assert bench.measured_traffic("rows_user_move", "msd_like", 64, "fp32") is None
