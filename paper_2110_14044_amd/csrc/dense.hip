@@ -267,6 +267,85 @@ __global__ __launch_bounds__(64) void k_gram_part(int32_t n, int32_t d, const fl
 // is multiplied.  The loads have no branches (rows past the chunk read its first row and
 // their weight z is 0), and the sets are never copied, so waiting for the current operands
 // does not wait for the ones in flight.
+// k_gram_vec with the rows read by buffer loads over the chunk: the descriptor's range ends at
+// the chunk's last row, so rows past it read as zeros (no masking), and every load takes its row
+// offset from one uniform register and its column offset from a per-lane constant (no address
+// arithmetic in the loop).  Needs (rows_per_chunk + 160) * d * 4 < 2^31.
+__global__ __launch_bounds__(256, 2) void k_gram_buf(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
+                                                  int32_t ncols, int32_t rows_per_chunk, float* __restrict__ part) {
+    __shared__ floatx4 red[3][16][64];
+    // the wavefront index is uniform; saying so keeps the row offset of the loads in a scalar register
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, q16 = lane & 15,
+              g4 = lane >> 4;
+    const int f0 = blockIdx.x * 64, q0 = blockIdx.y * 64;
+    const int64_t r0 = (int64_t)blockIdx.z * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int nbytes = (int)std::max<int64_t>(0, (r1 - r0) * d * 4);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X + (size_t)r0 * d), (short)0, nbytes, 0x00020000);
+    int oa[4], ob[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        oa[s] = ((4 * s + g4) * d + f0 + 4 * q16) * 4;
+        ob[s] = ((4 * s + g4) * d + p0 + q0 + 4 * q16) * 4;
+    }
+    floatx4 a0[4], b0[4], a1[4], b1[4];
+    auto load = [&](int rel, floatx4* a, floatx4* b) {
+        const int so = rel * d * 4;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            a[s] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, oa[s], so, 0));
+            b[s] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, ob[s], so, 0));
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the next MFMA block
+    };
+    auto mma = [&](const floatx4* a, const floatx4* b) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+                for (int qt = 0; qt < 4; ++qt) acc[ft][qt] = mfma4(a[s][ft], b[s][qt], acc[ft][qt]);
+    };
+    const int rows = (int)(r1 - r0);
+    int rel = 16 * wave;
+    load(rel, a0, b0);
+    for (; rel < rows; rel += 128) {
+        load(rel + 64, a1, b1);
+        mma(a0, b0);
+        load(rel + 128, a0, b0);
+        mma(a1, b1);
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) red[wave - 1][4 * ft + qt][lane] = acc[ft][qt];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) acc[ft][qt] += red[w][4 * ft + qt][lane];
+    float* out = part + (size_t)blockIdx.z * d * ncols + q0 + 4 * q16;
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int f = f0 + 4 * (4 * g4 + j) + ft;
+            *reinterpret_cast<float4*>(out + (size_t)f * ncols) =
+                make_float4(acc[ft][0][j], acc[ft][1][j], acc[ft][2][j], acc[ft][3][j]);
+        }
+}
+
 __global__ __launch_bounds__(256, 2) void k_gram_vec(int32_t n, int32_t d, const float* __restrict__ X, int32_t p0,
                                                   int32_t ncols, int32_t rows_per_chunk, float* __restrict__ part) {
     __shared__ floatx4 red[3][16][64];
@@ -1032,6 +1111,9 @@ void launch_gramian_raw(hipStream_t st, const float* X, int32_t n, int32_t d, in
         if (bf16)
             hipLaunchKernelGGL(k_gram_vec_bf16, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d,
                                X, p0, ncols, rv, part);
+        else if (((int64_t)rv + 160) * d * 4 < ((int64_t)1 << 31))
+            hipLaunchKernelGGL(k_gram_buf, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d, X,
+                               p0, ncols, rv, part);
         else
             hipLaunchKernelGGL(k_gram_vec, dim3((unsigned)ft, (unsigned)qg, (unsigned)cv), dim3(256), 0, st, n, d, X,
                                p0, ncols, rv, part);
