@@ -43,6 +43,34 @@ def test_wide_long_rows_in_segments(b):
     assert st["segments_item"] > 0 and st["long_rows_item"] > 0
 
 
+@pytest.mark.parametrize("b", [128, 256])
+def test_wide_block_wider_than_the_partner_side(b):
+    """Fewer items (96) than block coordinates: every user's block Hessian alpha0 G_pipi + lambda I
+    + sum a h h^T has rank at most 96 beyond the lambda I term, so its condition number is about
+    1 + alpha0 |G| / lambda (~1e5 here) and float32 solves cannot reproduce the float64 embeddings
+    to 1e-4.  What the method fixes is the objective: each block step minimises a convex quadratic,
+    whose value is insensitive to errors along the poorly determined directions.  Bars: the loss
+    after each of two epochs within 1e-6 relative of the float64 oracle, the embeddings within 1e-2
+    (both errors printed)."""
+    import oracle
+    from tests.gpu_util import oracle_setup, rel
+    p = synth.small_problem(360 + b, 4000, 96, 40_000, 256, b, labels=True, std=0.1)
+    tr = gpu_trainer(p)
+    csr, ys, as_ = oracle_setup(p)
+    out = []
+    for e in (1, 2):
+        tr.epoch(1)
+        W, H, _, losses = oracle.epochs(csr, p.W0, p.H0, b, p.alpha0, p.lam, e, ys, as_)
+        L = tr.loss()[0]
+        out.append((abs(L - losses[-1]) / abs(losses[-1]), rel(host(tr.W), W), rel(host(tr.H), H)))
+    st = tr.stats()
+    tr.close()
+    say(f"b={b}, 96 items: per epoch (loss, W, H) errors {[tuple(f'{x:.1e}' for x in o) for o in out]}, "
+        f"{st['fallback_rows']} rows redone in float64")
+    for el, ew, eh in out:
+        assert el < 1e-6 and ew < 1e-2 and eh < 1e-2
+
+
 def test_wide_long_rows_in_segment_groups():
     # segments of 256 observations: the longest item row has more than 8 segments, so the
     # partials are summed in groups before the row kernel adds them
