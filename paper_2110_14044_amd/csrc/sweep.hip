@@ -148,7 +148,10 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
     // all loaded before any is used (steps past the chunk load a valid row and contribute
     // nothing, their weight being 0), so the loads of a batch are in flight together.
     static_assert(U == 2 || U == 4 || U == 8, "batches of 2, 4 or 8 steps");
-    static_assert(!BF || U % 4 == 0, "a bfloat16 product takes four steps");
+    // a bfloat16 product takes four steps (K = 16: four values per lane group); with two-step
+    // batches the product's other two values are zero (half the product unused, for registers)
+    constexpr int BFS = U < 4 ? 2 : 4;
+    static_assert(!BF || U % BFS == 0, "bfloat16 products of two or four steps");
     const int q16 = lane & 15, g4 = lane >> 4;
     for (int64_t c0 = lo; c0 < hi; c0 += 64) {
         const int64_t k = c0 + lane;
@@ -219,12 +222,17 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
             if constexpr (BF) {
                 // four steps per bfloat16 product; a weight of 0 zeroes a padding step's terms
 #pragma unroll
-                for (int h = 0; h < U; h += 4) {
+                for (int h = 0; h < U; h += BFS) {
                     shortx4 pa[NT], pb[NT];
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        pa[t] = bf16x4(xa4[h][t], xa4[h + 1][t], xa4[h + 2][t], xa4[h + 3][t]);
-                        pb[t] = bf16x4(x[h][t], x[h + 1][t], x[h + 2][t], x[h + 3][t]);
+                        if constexpr (BFS == 4) {
+                            pa[t] = bf16x4(xa4[h][t], xa4[h + 1][t], xa4[h + 2][t], xa4[h + 3][t]);
+                            pb[t] = bf16x4(x[h][t], x[h + 1][t], x[h + 2][t], x[h + 3][t]);
+                        } else {
+                            pa[t] = bf16x4(xa4[h][t], xa4[h + 1][t], 0.f, 0.f);
+                            pb[t] = bf16x4(x[h][t], x[h + 1][t], 0.f, 0.f);
+                        }
                     }
                     int id = 0;
 #pragma unroll
@@ -779,7 +787,7 @@ __device__ __forceinline__ void w8_back(const floatx4* acc, float* lds, int lane
 }
 
 template <bool FULL, bool TRANS, bool BF>
-__global__ __launch_bounds__(256, BF ? 1 : 2) void k_rows_w8(SweepArgs A) {
+__global__ __launch_bounds__(256, 2) void k_rows_w8(SweepArgs A) {
     constexpr int NT = 8, B = 128, NTL = 36;
     extern __shared__ float lds_w8[];
     const int wave = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
@@ -800,7 +808,7 @@ __global__ __launch_bounds__(256, BF ? 1 : 2) void k_rows_w8(SweepArgs A) {
         if (sf < 0) {
             float own[NT], ownc[TRANS ? NT : 1];
             load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
-            accumulate<NT, FULL, TRANS, BF, BF ? 4 : 2>(A, lo, hi, own, ownc, acc, gp, lane);
+            accumulate<NT, FULL, TRANS, BF, 2>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
