@@ -129,7 +129,9 @@ __device__ inline void icd_obs(const IcdArgs& A, int64_t lo, int64_t hi, float x
 template <bool TRANS>
 __global__ __launch_bounds__(256) void k_icd_seg(IcdArgs A) {
     const int lane = threadIdx.x & 63;
-    for (int sidx = blockIdx.x * 4 + (threadIdx.x >> 6); sidx < A.nseg; sidx += gridDim.x * 4) {
+    // uniform wavefront index: the segment index and its bounds are scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int sidx = blockIdx.x * 4 + wave; sidx < A.nseg; sidx += gridDim.x * 4) {
         const int r = A.seg_row[sidx];
         const float xf = A.X[(size_t)r * A.d + A.f];
         const float xp = TRANS ? A.X[(size_t)r * A.d + A.pc] : 0.f;
@@ -147,7 +149,8 @@ __global__ __launch_bounds__(256) void k_icd_seg(IcdArgs A) {
 template <bool TRANS>
 __global__ __launch_bounds__(256) void k_icd_rows(IcdArgs A) {
     const int lane = threadIdx.x & 63;
-    for (int it = blockIdx.x * 4 + (threadIdx.x >> 6); it < A.nrows; it += gridDim.x * 4) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int it = blockIdx.x * 4 + wave; it < A.nrows; it += gridDim.x * 4) {
         const int r = A.order[it];
         float* xr = A.X + (size_t)r * A.d;
         const float xf = xr[A.f];

@@ -265,7 +265,10 @@ template <int NT, bool FULL, bool TRANS, bool BF>
 __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
     constexpr int NTL = ntiles<NT>();
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
-    for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < A.nseg; j += gridDim.x * 4) {
+    // the wavefront index made uniform, so that the segment and row indices, the row bounds and
+    // the loops over them live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int j = blockIdx.x * 4 + wave; j < A.nseg; j += gridDim.x * 4) {
         const int it = A.seg_order[j];
         floatx4 acc[NTL];
         float gp[NT], own[NT], ownc[TRANS ? NT : 1];
@@ -332,17 +335,23 @@ __global__ __launch_bounds__(256) void k_seg_group(SweepArgs A, int32_t stride) 
 }
 
 // Blocked factorisation storage: panel K (16 columns, rows 16K..B-1) of the factor L is
-// kept in LDS with row stride kPS; panels are packed one after another.  A stride of 20
-// floats keeps rows 16-byte aligned and spreads the accesses over the banks: the
-// accumulator-layout stores (rows 4 apart in a half-wave), the lane-per-row 16-byte loads
-// (8 rows per cycle) and the operand loads of the trailing updates.
+// kept in LDS, panels packed one after another.  The 128-wide kernel keeps one panel at a
+// row stride of kPS = 20 floats, which keeps rows 16-byte aligned and spreads the accesses
+// over the banks (the accumulator-layout stores, rows 4 apart in a half-wave; the
+// lane-per-row 16-byte loads; the operand loads of the trailing updates).  The narrow kernel
+// keeps all of its panels for the back substitution at a stride of kPN = 16 floats: 10 KB
+// per wavefront, so that four 4-wavefront blocks fit a CU's 160 KB of LDS and each SIMD
+// holds four wavefronts (with a stride of 20 it held three; the accumulator-layout stores
+// and the trailing-update operand loads then meet 4-way bank conflicts, which cost less
+// than the fourth wavefront gains).
 constexpr int kPS = 20;
+constexpr int kPN = 16;
 template <int NT>
 constexpr int panel_rows() { return 16 * NT * (NT + 1) / 2; }
 template <int NT>
 __host__ __device__ constexpr int panel_row0(int K) { return 16 * (K * NT - K * (K - 1) / 2); }
 template <int NT>
-constexpr int rows_lds_floats_per_wave() { return panel_rows<NT>() * kPS; }
+constexpr int rows_lds_floats_per_wave() { return panel_rows<NT>() * kPN; }
 template <int NT>
 constexpr int rows_lds_floats() { return 4 * rows_lds_floats_per_wave<NT>(); }
 
@@ -360,28 +369,32 @@ __global__ void k_make_dtiles(const float* __restrict__ Dmat, float* __restrict_
     dtiles[e] = Dmat[colmap<NT, FULL>(16 * ti + 4 * (lq >> 4) + j) * B + colmap<NT, FULL>(16 * tj + (lq & 15))];
 }
 
-// Zero rows read by the back substitution in place of panel rows a lane does not use.
-constexpr int kZeroFloats = 16 * kPS;
-
 // Steps KK..15 of panel K (see ldl_solve).  src: ds_bpermute address of the lane of row
 // group K in this lane's row position; lk = this lane's row - 16K (-1 - 16K past the block).
+// piv and D were read for this step by the previous one: each step updates column k + 1
+// first and at once reads the next pivot and starts the next copy of the pivot column, so
+// that their latency runs under the step's other column updates (look-ahead).
 template <int K, int KK>
-__device__ inline void panel_steps(float* p, float& g, float& mypiv, float lk, int src) {
+__device__ inline void panel_steps(float* p, float& g, float& mypiv, float lk, int src, float piv, float D) {
     if constexpr (KK < 16) {
         constexpr int k = 16 * K + KK;
-        const float piv = readlane(p[KK], k);
-        // lane k keeps the pivot (two wait states: piv was just written by a VALU readlane)
+        // lane k keeps the pivot
         asm volatile("s_nop 1\n\tv_writelane_b32 %0, %1, %2" : "+v"(mypiv) : "s"(piv), "i"(k));
         const float nr = __builtin_amdgcn_rcpf(-piv);
         const float act = __builtin_amdgcn_fmed3f(lk - (float)KK, 0.f, 1.f);  // 1 in the lanes below row k
         const float tn = p[KK] * nr * act;              // -t_i
+        float pivn = 0.f, Dn = 0.f;
         if constexpr (KK < 15) {
-            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p[KK])));
-            eliminate_cols<KK + 1, true>(p, D, tn);
+            fmac_rowbcast<KK + 1, true>(p[KK + 1], D, tn);
+            pivn = readlane(p[KK + 1], k + 1);
+            if constexpr (KK < 14) Dn = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p[KK + 1])));
+            // keep the reads of the next step ahead of this step's other updates
+            __builtin_amdgcn_sched_barrier(0);
+            eliminate_cols<KK + 2, false>(p, D, tn);
         }
         g = fmaf(tn, readlane(g, k), g);
         p[KK] = tn;
-        panel_steps<K, KK + 1>(p, g, mypiv, lk, src);
+        panel_steps<K, KK + 1>(p, g, mypiv, lk, src, pivn, Dn);
     }
 }
 
@@ -403,12 +416,12 @@ __device__ inline void ldl_panels(floatx4* acc, float& g, float* pan, int ln, fl
     if constexpr (K < NT) {
         constexpr int B = 16 * NT;
         const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
-        float* PK = pan + panel_row0<NT>(K) * kPS;  // row r >= 16K at PK + (r - 16K) * kPS
+        float* PK = pan + panel_row0<NT>(K) * kPN;  // row r >= 16K at PK + (r - 16K) * kPN
 #pragma unroll
         for (int I = K; I < NT; ++I) {
             const int id = I * (I + 1) / 2 + K;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) PK[(16 * (I - K) + 4 * g4 + j) * kPS + q16] = acc[id][j];
+            for (int j = 0; j < 4; ++j) PK[(16 * (I - K) + 4 * g4 + j) * kPN + q16] = acc[id][j];
         }
         wave_lds_fence();
         const bool mine = (ln >= 16 * K) && (ln < B);
@@ -416,18 +429,23 @@ __device__ inline void ldl_panels(floatx4* acc, float& g, float* pan, int ln, fl
         float p[16];
 #pragma unroll
         for (int c4 = 0; c4 < 4; ++c4) {
-            const float4 v = *reinterpret_cast<const float4*>(PK + prow * kPS + 4 * c4);
+            const float4 v = *reinterpret_cast<const float4*>(PK + prow * kPN + 4 * c4);
             p[4 * c4 + 0] = v.x;
             p[4 * c4 + 1] = v.y;
             p[4 * c4 + 2] = v.z;
             p[4 * c4 + 3] = v.w;
         }
         wave_lds_fence();
-        panel_steps<K, 0>(p, g, mypiv, li - 16.f * K, (16 * K + (ln & 15)) * 4);
+        {
+            const int src = (16 * K + (ln & 15)) * 4;
+            const float piv0 = readlane(p[0], 16 * K);
+            const float D0 = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p[0])));
+            panel_steps<K, 0>(p, g, mypiv, li - 16.f * K, src, piv0, D0);
+        }
         if (mine) {
 #pragma unroll
             for (int c4 = 0; c4 < 4; ++c4)
-                *reinterpret_cast<float4*>(PK + prow * kPS + 4 * c4) =
+                *reinterpret_cast<float4*>(PK + prow * kPN + 4 * c4) =
                     make_float4(p[4 * c4], p[4 * c4 + 1], p[4 * c4 + 2], p[4 * c4 + 3]);
         }
         wave_lds_fence();
@@ -439,7 +457,7 @@ __device__ inline void ldl_panels(floatx4* acc, float& g, float* pan, int ln, fl
                     __builtin_amdgcn_ds_bpermute((16 * K + 4 * s4 + g4) * 4, __float_as_int(mypiv)));
                 float op[NT];
 #pragma unroll
-                for (int I = K + 1; I < NT; ++I) op[I] = PK[(16 * (I - K) + q16) * kPS + 4 * s4 + g4];
+                for (int I = K + 1; I < NT; ++I) op[I] = PK[(16 * (I - K) + q16) * kPN + 4 * s4 + g4];
 #pragma unroll
                 for (int I = K + 1; I < NT; ++I) {
                     const float a = op[I] * npm;
@@ -475,7 +493,7 @@ __device__ inline float diag_max(const floatx4* acc, int lane, int bw) {
 }
 
 template <int NT, bool FULL>
-__device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, const float* zero_lds, int ln, float tau,
+__device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, int ln, float tau,
                                  int my_col, int bw, float& x) {
     constexpr int B = 16 * NT;
     const float li = (ln < B) ? (float)ln : -1.f;  // lanes past the block never take a step
@@ -498,17 +516,19 @@ __device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, const float*
     if (bad) return false;
     // w = D^-1 L^-1 g, then L^T x = w from the last column: x_k = w_k once every later column
     // has been applied, then w_i += (-L_ki) x_k for i < k (lane i reads row k of the panel
-    // that holds column i; lanes whose panel comes after row k read zeros).
+    // that holds column i; lanes whose panel comes after row k read column 15 of panel K's
+    // diagonal tile, which is zero in every row: the stored panels hold zeros on and above
+    // the diagonal).
     float wv = g * __builtin_amdgcn_rcpf(mypiv);
     const int pk = ln >> 4;
     const int pbase = panel_row0<NT>(pk < NT ? pk : 0) - 16 * pk;
 #pragma unroll
     for (int K = NT - 1; K >= 0; --K) {
         const bool ok = (pk <= K) && (ln < B);
-        const float* rowp = ok ? pan + (pbase + 16 * K) * kPS + (ln & 15) : zero_lds + (ln & 15);
+        const float* rowp = ok ? pan + (pbase + 16 * K) * kPN + (ln & 15) : pan + panel_row0<NT>(K) * kPN + 15;
         float lt[16];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) lt[jj] = rowp[jj * kPS];
+        for (int jj = 0; jj < 16; ++jj) lt[jj] = rowp[jj * kPN];
 #pragma unroll
         for (int jj = 15; jj >= 0; --jj) wv = fmaf(lt[jj], readlane(wv, 16 * K + jj), wv);
         __builtin_amdgcn_sched_barrier(0);
@@ -519,14 +539,11 @@ __device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, const float*
 }
 
 template <int NT, bool FULL, bool TRANS, bool STATIC, bool BF>
-__global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
+__global__ __launch_bounds__(256, 4) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
     float* pan = lds_all + wave * rows_lds_floats_per_wave<NT>();
-    float* zero_lds = lds_all + rows_lds_floats<NT>();
-    for (int e = threadIdx.x; e < kZeroFloats; e += 256) zero_lds[e] = 0.f;
-    __syncthreads();
     const int my_col = colmap<NT, FULL>(lane < B ? lane : 0);
 
     // STATIC: rows are dealt round-robin in the length order (sides whose rows are all
@@ -572,19 +589,19 @@ __global__ __launch_bounds__(256, 3) void k_sweep_rows(SweepArgs A) {
                 for (int t = 0; t < NT; ++t) gp[t] += pg[t];
             }
         }
+        // The lane id is laundered once per row so that the lane-dependent values below
+        // are formed inside the row, not hoisted out of the row loop into registers.
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int my_col = colmap<NT, FULL>(ln < B ? ln : 0);
         // lane p < B holds the gradient entry of position p
         float g = 0.f;
 #pragma unroll
         for (int t = 0; t < NT; ++t)
             if (g4 == t) g = gp[t];
         if (lane < B) g += A.R0[(size_t)r * B + my_col];
-
-        // The lane id is laundered once per row so that the lane-dependent values below
-        // are formed inside the row, not hoisted out of the row loop into registers.
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
         float w;
-        if (!ldl_solve<NT, FULL>(acc, g, pan, zero_lds, ln, A.tau, my_col, A.bw, w)) {
+        if (!ldl_solve<NT, FULL>(acc, g, pan, ln, A.tau, my_col, A.bw, w)) {
             // a pivot was rejected: the row is redone in float64
             if (lane == 0) {
                 const int pos = atomicAdd(&A.cursors[CUR_FB_LIST], 1);
@@ -620,19 +637,25 @@ struct W8Lds {
     static constexpr int PER_WAVE = YS + 16;
 };
 
+// Steps KK..15 of panel K of the 128-wide LDL^T, with the look-ahead of panel_steps: piv and
+// D (the pivot column of the panel's first row group, copied to every row group) were read
+// for this step by the previous one.
 template <int K, int KK>
 __device__ __forceinline__ void w8_steps(float* p1, float* p2, float& g1, float& g2, float* pvl, float li, int src,
-                                bool lead) {
+                                bool lead, float piv, float D) {
     if constexpr (KK < 16) {
-        const float piv = readlane(p1[KK], KK);
         if (lead) pvl[16 * K + KK] = piv;
         const float nr = __builtin_amdgcn_rcpf(-piv);
         const float act = __builtin_amdgcn_fmed3f(li - (float)KK, 0.f, 1.f);  // 1 for the rows below KK
         const float tn1 = p1[KK] * nr * act;                                 // -t_i
         const float tn2 = K < 4 ? p2[KK] * nr : 0.f;                          // set 2: all below
+        float pivn = 0.f, Dn = 0.f;
         if constexpr (KK < 15) {
-            const float D = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p1[KK])));
-            eliminate_cols<KK + 1, true>(p1, D, tn1);
+            fmac_rowbcast<KK + 1, true>(p1[KK + 1], D, tn1);
+            pivn = readlane(p1[KK + 1], KK + 1);
+            if constexpr (KK < 14) Dn = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p1[KK + 1])));
+            __builtin_amdgcn_sched_barrier(0);
+            eliminate_cols<KK + 2, false>(p1, D, tn1);
             if constexpr (K < 4) eliminate_cols<KK + 1, true>(p2, D, tn2);
         }
         const float gk = readlane(g1, KK);
@@ -642,7 +665,7 @@ __device__ __forceinline__ void w8_steps(float* p1, float* p2, float& g1, float&
             g2 = fmaf(tn2, gk, g2);
             p2[KK] = tn2;
         }
-        w8_steps<K, KK + 1>(p1, p2, g1, g2, pvl, li, src, lead);
+        w8_steps<K, KK + 1>(p1, p2, g1, g2, pvl, li, src, lead, pivn, Dn);
     }
 }
 
@@ -689,7 +712,12 @@ __device__ __forceinline__ void w8_panels(floatx4* acc, float* lds, int lane) {
         float g1 = v1 ? GL[16 * K + lane] : 0.f;
         float g2 = v2 ? GL[16 * K + 64 + lane] : 0.f;
         wave_lds_fence();
-        w8_steps<K, 0>(p1, p2, g1, g2, PV, v1 ? (float)lane : -1.f, (lane & 15) * 4, lane == 0);
+        {
+            const int src = (lane & 15) * 4;
+            const float piv0 = readlane(p1[0], 0);
+            const float D0 = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p1[0])));
+            w8_steps<K, 0>(p1, p2, g1, g2, PV, v1 ? (float)lane : -1.f, src, lane == 0, piv0, D0);
+        }
         // the panel as -L (zeros on and above the diagonal), the updated gradient, and a copy
         // of the diagonal tile for the back substitution
         if (v1) {
@@ -986,7 +1014,7 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
         launch_seg_group(st, args, seg_stride<NT>());
     }
     if (s.nrows > 0) {
-        const size_t lds = sizeof(float) * (rows_lds_floats<NT>() + kZeroFloats);
+        const size_t lds = sizeof(float) * rows_lds_floats<NT>();
         hipLaunchKernelGGL((k_make_dtiles<NT, FULL>), dim3((ntiles<NT>() * 256 + 255) / 256), dim3(256), 0, st, args.Dmat,
                            args.dtiles);
         {
