@@ -156,49 +156,73 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
     for (int64_t c0 = lo; c0 < hi; c0 += 64) {
         const int64_t k = c0 + lane;
         const bool v = k < hi;
+        // Per observation (one per lane): the partner id, the cache slot, the cache entry less
+        // the label (with TRANS the cache entry and the label apart) and the weight, 0 past
+        // the chunk, so that padding steps add nothing without a test of their own.
         int ci = 0, si = 0;
-        float cv = 0.f, yv = 1.f, av = 1.f;
+        float cv = 0.f, yv = 1.f, av = TRANS ? 1.f : 0.f;
         if (v) {
             ci = A.col[k];
             si = A.slot ? A.slot[k] : (int)k;
             cv = A.cache[si];
             if (A.y) yv = A.y[k];
-            if (A.a) av = A.a[k];
+            if constexpr (TRANS) {
+                if (A.a) av = A.a[k];
+            } else {
+                av = A.a ? A.a[k] : 1.f;
+            }
         }
+        if constexpr (!TRANS) cv -= yv;
         const int cnt = (int)std::min<int64_t>(64, hi - c0);
         const int nsteps = (cnt + 3) >> 2;
         for (int st = 0; st < nsteps; st += U) {
             float x[U][NT], xc[U][TRANS ? NT : 1];
             float xa4[BF ? U : 1][NT];
+            // Without TRANS: ds_bpermute byte address of lane 4 st + g4, the observation of
+            // step st in this lane group (step st + u at +16 u; st + u < 16, so no wrap), and
+            // the label and the padding folded into the permuted values.  The passes that move
+            // the cache keep lane-index shuffles, the label and weight permuted only when
+            // given and the validity test their cache store needs anyway (the same form with
+            // the folded values measured slower there).
+            const int sa = 16 * st + 4 * g4;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int i = __shfl(ci, (4 * (st + u) + g4) & 63);
+                const int i = TRANS ? __shfl(ci, (4 * (st + u) + g4) & 63) : __builtin_amdgcn_ds_bpermute(sa + 16 * u, ci);
                 load_cols<NT, FULL>(A.Xo, A.d, i, A.p0, A.bw, q16, x[u]);
                 if constexpr (TRANS) load_cur<NT>(A, A.Xo, i, q16, xc[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int src = 4 * (st + u) + g4;
-                const bool valid = src < cnt;
-                const float ck = __shfl(cv, src & 63);
-                const float yk = A.y ? __shfl(yv, src & 63) : 1.f;
-                const float ak_all = A.a ? __shfl(av, src & 63) : 1.f;
-                const float ak = valid ? ak_all : 0.f;
-                float sp = 0.f;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
-                sp = sum16(sp);
-                float yh = ck + sp;
+                // residual yhat - y: with TRANS from the cache's block, else from this block
+                float ak, res, sp = 0.f;
                 if constexpr (TRANS) {
+                    const int src = 4 * (st + u) + g4;
+                    const bool valid = src < cnt;
+                    const float ck = __shfl(cv, src & 63);
+                    const float yk = A.y ? __shfl(yv, src & 63) : 1.f;
+                    const float ak_all = A.a ? __shfl(av, src & 63) : 1.f;
+                    ak = valid ? ak_all : 0.f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
+                    sp = sum16(sp);
                     float sc = 0.f;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) sc = fmaf(xc[u][t], ownc[t], sc);
                     sc = sum16(sc);
-                    yh = ck + sc;
+                    const float yh = ck + sc;
+                    res = yh - yk;
                     const int sk = __shfl(si, src & 63);
                     if (q16 == 0 && valid) A.cache[sk] = yh - sp;
+                } else {
+                    const int sau = sa + 16 * u;
+                    const float ck = __int_as_float(__builtin_amdgcn_ds_bpermute(sau, __float_as_int(cv)));
+                    ak = __int_as_float(__builtin_amdgcn_ds_bpermute(sau, __float_as_int(av)));
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) sp = fmaf(x[u][t], own[t], sp);
+                    sp = sum16(sp);
+                    res = ck + sp;
                 }
-                const float rk = ak * (yh - yk);
+                const float rk = ak * res;
                 float xa[NT];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
