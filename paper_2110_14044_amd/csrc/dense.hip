@@ -167,6 +167,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     }
 }
 
+// The same over the columns [f0, f0 + 256 J) of rows of d columns: the first slice writes
+// its partial dot products (on top of base with inside), the later ones add theirs.  Slices
+// whose rows of H fit the Infinity Cache (256 MB) are re-read from it instead of HBM: the
+// observations of a user visit random items, each item row about |S| / |I| times per pass.
+template <int J, int UB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_predict_slice(
+    int32_t U, int32_t d, int32_t f0, bool first, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+    const float* __restrict__ W, const float* __restrict__ H, int32_t p0, int32_t bw, bool inside,
+    const float* __restrict__ base, float* __restrict__ out) {
+    const int u = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (u >= U) return;
+    float4 w[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int f = f0 + 4 * lane + 256 * j;
+        // each row of W is read once per pass: streamed past the caches
+        const floatx4 nv = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(W + (size_t)u * d + f));
+        float4 v = make_float4(nv[0], nv[1], nv[2], nv[3]);
+        v.x = ((f + 0 >= p0 && f + 0 < p0 + bw) == inside) ? v.x : 0.f;
+        v.y = ((f + 1 >= p0 && f + 1 < p0 + bw) == inside) ? v.y : 0.f;
+        v.z = ((f + 2 >= p0 && f + 2 < p0 + bw) == inside) ? v.z : 0.f;
+        v.w = ((f + 3 >= p0 && f + 3 < p0 + bw) == inside) ? v.w : 0.f;
+        w[j] = v;
+    }
+    const int64_t lo = ptr[u], hi = ptr[u + 1];
+    for (int64_t c0 = lo; c0 < hi; c0 += 64) {
+        const int64_t k = c0 + lane;
+        const int ci = (k < hi) ? col[k] : 0;
+        const int cnt = (int)min((int64_t)64, hi - c0);
+        float mine = 0.f;  // lane t keeps the partial prediction of observation c0 + t
+        for (int t0 = 0; t0 < cnt; t0 += UB) {
+            float4 h[UB][J];
+#pragma unroll
+            for (int v = 0; v < UB; ++v) {
+                const int i = __shfl(ci, (t0 + v) & 63);  // past the chunk: a valid row, result unused
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    h[v][j] = *reinterpret_cast<const float4*>(H + (size_t)i * d + f0 + 4 * lane + 256 * j);
+            }
+#pragma unroll
+            for (int v = 0; v < UB; ++v) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    s = fmaf(w[j].x, h[v][j].x, s);
+                    s = fmaf(w[j].y, h[v][j].y, s);
+                    s = fmaf(w[j].z, h[v][j].z, s);
+                    s = fmaf(w[j].w, h[v][j].w, s);
+                }
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+                if (lane == t0 + v) mine = s;
+            }
+        }
+        if (lane < cnt) {
+            const float prev = first ? (inside ? base[c0 + lane] : 0.f) : out[c0 + lane];
+            out[c0 + lane] = prev + mine;
+        }
+    }
+}
+
 // Partial Gramian of one row chunk: part[chunk][f][q] = sum_{r in chunk} X[r][f] X[r][p0+q]
 // for f < d, q < ncols (columns q >= bw are zero).  Block = one wavefront owning a
 // 64 x (16*QT) output tile (4 x QT MFMA tiles).  BF: bfloat16 operands (16 rows per
@@ -1070,9 +1132,12 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
     else if (c->d == 1024)
         hipLaunchKernelGGL((k_predict_wide<4, 4>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
                            p0, bw, inside, c->yhat, out);
-    else if (c->d == 2048)
-        hipLaunchKernelGGL((k_predict_wide<8, 2>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
-                           p0, bw, inside, c->yhat, out);
+    else if (c->d == 2048) {
+        // two slices of 1,024 columns: 168 MB of H per slice at the MSD shape
+        for (int f0 = 0; f0 < 2048; f0 += 1024)
+            hipLaunchKernelGGL((k_predict_slice<4, 4>), dim3(g), dim3(256), 0, c->stream, c->U, c->d, f0, f0 == 0,
+                               us.ptr, us.col, c->W, c->H, p0, bw, inside, c->yhat, out);
+    }
     else
         hipLaunchKernelGGL(k_predict, dim3(g), dim3(256), 0, c->stream, c->U, c->d, us.ptr, us.col, c->W, c->H, p0, bw,
                            inside, c->yhat, out);
