@@ -865,22 +865,25 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
 // consecutive k-steps of column 16 t + q16).  Two slices alternate: the next one is loaded
 // while the current one is multiplied, one barrier per 16 columns of f.  Rows past n read row
 // 0 and are never written.
+// RT: row tiles of 16 per wavefront (4: 64 rows; 1 for tables with too few rows to give every
+// CU a block at 256 rows per block, such as the item side at the MSD shape).
 constexpr int kGsPitch = 20;
+template <int RT>
 __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
                                                    const float* __restrict__ G, int32_t p0, int32_t bw, float alpha0,
                                                    float lambda, float* __restrict__ R0) {
     __shared__ __align__(16) float gs[2][64 * kGsPitch];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q16 = lane & 15, g4 = lane >> 4;
     const int qb = 64 * blockIdx.y;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
-    floatx4 acc[4][4];
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+    floatx4 acc[RT][4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[rt][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* xr[4];
+    const float* xr[RT];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         const int64_t r = r0 + 16 * rt + q16;
         xr[rt] = X + (size_t)(r < n ? r : 0) * d + 4 * g4;
     }
@@ -898,7 +901,7 @@ __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t
     auto xload = [&](int fb, floatx4* a) {
         const int f = fb < d ? fb : 0;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) a[rt] = *reinterpret_cast<const floatx4*>(xr[rt] + f);
+        for (int rt = 0; rt < RT; ++rt) a[rt] = *reinterpret_cast<const floatx4*>(xr[rt] + f);
     };
     auto mma = [&](int buf, const floatx4* a) {
         floatx4 b[4];
@@ -907,11 +910,11 @@ __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[rt][t] = mfma4(a[rt][s], b[t][s], acc[rt][t]);
     };
-    floatx4 a0[4], a1[4];
+    floatx4 a0[RT], a1[RT];
     gstore(0, gload(0));
     xload(0, a0);
     __syncthreads();
@@ -932,7 +935,7 @@ __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t
     }
     if (r0 >= n) return;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -1218,8 +1221,12 @@ void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw
     const int B = c->B;
     if (B % 64 == 0 && c->d % 32 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(c->G) % 16 == 0) {
-        hipLaunchKernelGGL(k_dense_lds, dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X, c->G,
-                           p0, bw, c->alpha0, c->lambda, c->R0);
+        if ((int64_t)grid * (B / 64) >= 2 * (int64_t)c->num_cu)
+            hipLaunchKernelGGL((k_dense_lds<4>), dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X,
+                               c->G, p0, bw, c->alpha0, c->lambda, c->R0);
+        else
+            hipLaunchKernelGGL((k_dense_lds<1>), dim3(nblk(n, 64), (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d,
+                               B, X, c->G, p0, bw, c->alpha0, c->lambda, c->R0);
         return;
     }
     if (B % 64 == 0 && c->d % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
