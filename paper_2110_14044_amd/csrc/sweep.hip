@@ -141,7 +141,9 @@ __device__ inline void load_cur(const SweepArgs& A, const float* X, int i, int q
 // BF: the Hessian products take bfloat16 operands (one 16x16x16 MFMA per tile for the
 // four observations of every lane group, 16 in all); the gradient and the predictions
 // stay float32.
-template <int NT, bool FULL, bool TRANS, bool BF, int U = 4>
+// CF: the cache's block is a full block (vector loads of the partner rows' old block, no
+// per-step branch between the two load forms).
+template <int NT, bool FULL, bool TRANS, bool BF, int U = 4, bool CF = true>
 __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, const float* own, const float* ownc,
                                   floatx4* acc, float* gp, int lane) {
     // U steps of 4 observations per batch.  A batch has no branches: its partner rows are
@@ -189,7 +191,12 @@ __device__ inline void accumulate(const SweepArgs& A, int64_t lo, int64_t hi, co
             for (int u = 0; u < U; ++u) {
                 const int i = TRANS ? __shfl(ci, (4 * (st + u) + g4) & 63) : __builtin_amdgcn_ds_bpermute(sa + 16 * u, ci);
                 load_cols<NT, FULL>(A.Xo, A.d, i, A.p0, A.bw, q16, x[u]);
-                if constexpr (TRANS) load_cur<NT>(A, A.Xo, i, q16, xc[u]);
+                if constexpr (TRANS) {
+                    if constexpr (CF)
+                        load_cols<NT, (NT != 3)>(A.Xo, A.d, i, A.pc, A.bwc, q16, xc[u]);
+                    else
+                        load_cols<NT, false>(A.Xo, A.d, i, A.pc, A.bwc, q16, xc[u]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -285,7 +292,7 @@ __device__ inline void load_own(const SweepArgs& A, int r, int q16, float* own, 
     if constexpr (TRANS) load_cur<NT>(A, A.X, r, q16, ownc);
 }
 
-template <int NT, bool FULL, bool TRANS, bool BF>
+template <int NT, bool FULL, bool TRANS, bool BF, bool CF>
 __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
     constexpr int NTL = ntiles<NT>();
     const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(256) void k_sweep_seg(SweepArgs A) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) gp[t] = 0.f;
         load_own<NT, FULL, TRANS>(A, A.seg_row[it], q16, own, ownc);
-        accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
+        accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>, CF>(A, A.seg_lo[it], A.seg_hi[it], own, ownc, acc, gp, lane);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             gp[t] += __shfl_xor(gp[t], 16);
@@ -562,7 +569,7 @@ __device__ inline bool ldl_solve(floatx4* acc, float g, float* pan, int ln, floa
     return true;
 }
 
-template <int NT, bool FULL, bool TRANS, bool STATIC, bool BF>
+template <int NT, bool FULL, bool TRANS, bool STATIC, bool BF, bool CF>
 __global__ __launch_bounds__(256, 4) void k_sweep_rows(SweepArgs A) {
     constexpr int B = 16 * NT, NTL = ntiles<NT>();
     extern __shared__ float lds_all[];
@@ -589,7 +596,7 @@ __global__ __launch_bounds__(256, 4) void k_sweep_rows(SweepArgs A) {
         if (sf < 0) {
             float own[NT], ownc[TRANS ? NT : 1];
             load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
-            accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>>(A, lo, hi, own, ownc, acc, gp, lane);
+            accumulate<NT, FULL, TRANS, BF, kBatchSteps<TRANS, BF>, CF>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
@@ -838,7 +845,7 @@ __device__ __forceinline__ void w8_back(const floatx4* acc, float* lds, int lane
     }
 }
 
-template <bool FULL, bool TRANS, bool BF>
+template <bool FULL, bool TRANS, bool BF, bool CF>
 __global__ __launch_bounds__(256, 2) void k_rows_w8(SweepArgs A) {
     constexpr int NT = 8, B = 128, NTL = 36;
     extern __shared__ float lds_w8[];
@@ -860,7 +867,7 @@ __global__ __launch_bounds__(256, 2) void k_rows_w8(SweepArgs A) {
         if (sf < 0) {
             float own[NT], ownc[TRANS ? NT : 1];
             load_own<NT, FULL, TRANS>(A, r, q16, own, ownc);
-            accumulate<NT, FULL, TRANS, BF, 2>(A, lo, hi, own, ownc, acc, gp, lane);
+            accumulate<NT, FULL, TRANS, BF, 2, CF>(A, lo, hi, own, ownc, acc, gp, lane);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 gp[t] += __shfl_xor(gp[t], 16);
@@ -1027,13 +1034,13 @@ __global__ __launch_bounds__(256) void k_sweep_fallback(SweepArgs A) {
     }
 }
 
-template <int NT, bool FULL, bool TRANS, bool BF>
-void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+template <int NT, bool FULL, bool TRANS, bool BF, bool CF>
+void launch_sweep_nt_cf(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
     hipStream_t st = c->stream;
     const unsigned max_blocks = (unsigned)c->num_cu * 8;
     if (s.nseg > 0) {
         ProfScope ps(c, IALS_K_SEG_USER + sd);
-        hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS, BF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
+        hipLaunchKernelGGL((k_sweep_seg<NT, FULL, TRANS, BF, CF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
                            dim3(256), 0, st, args);
         launch_seg_group(st, args, seg_stride<NT>());
     }
@@ -1047,18 +1054,30 @@ void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int
                 // static dealing: exactly the blocks that are resident at once
                 static OccCache occ;
                 const int resident = resident_per_cu(
-                    occ, reinterpret_cast<const void*>(&k_sweep_rows<NT, FULL, TRANS, true, BF>), 256, lds, false, 2);
-                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true, BF>),
+                    occ, reinterpret_cast<const void*>(&k_sweep_rows<NT, FULL, TRANS, true, BF, CF>), 256, lds, false, 2);
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, true, BF, CF>),
                                    dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
                                    dim3(256), lds, st, args);
             } else {
-                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, false, BF>),
+                hipLaunchKernelGGL((k_sweep_rows<NT, FULL, TRANS, false, BF, CF>),
                                    dim3(std::min<unsigned>(max_blocks, (s.nrows + 3) / 4)), dim3(256), lds, st, args);
             }
         }
         ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
         hipLaunchKernelGGL((k_sweep_fallback<NT>), dim3((unsigned)c->num_cu), dim3(256), 0, st, args);
     }
+}
+
+// the passes that move the cache come in two forms, by whether the cache's block is full
+template <int NT, bool FULL, bool TRANS, bool BF>
+void launch_sweep_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+    if constexpr (TRANS) {
+        if (!args.cur_full) {
+            launch_sweep_nt_cf<NT, FULL, TRANS, BF, false>(c, args, s, sd);
+            return;
+        }
+    }
+    launch_sweep_nt_cf<NT, FULL, TRANS, BF, true>(c, args, s, sd);
 }
 
 template <int NT>
@@ -1095,13 +1114,13 @@ void launch_sweep_prec(ials_ctx* c, SweepArgs& A, const SideIndex& s, int sd, bo
     }
 }
 
-template <bool FULL, bool TRANS, bool BF>
-void launch_w8_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+template <bool FULL, bool TRANS, bool BF, bool CF>
+void launch_w8_nt_cf(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
     hipStream_t st = c->stream;
     const unsigned max_blocks = (unsigned)c->num_cu * 8;
     if (s.nseg > 0) {
         ProfScope ps(c, IALS_K_SEG_USER + sd);
-        hipLaunchKernelGGL((k_sweep_seg<8, FULL, TRANS, BF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
+        hipLaunchKernelGGL((k_sweep_seg<8, FULL, TRANS, BF, CF>), dim3(std::min<unsigned>(max_blocks, (s.nseg + 3) / 4)),
                            dim3(256), 0, st, args);
         launch_seg_group(st, args, seg_stride<8>());
     }
@@ -1114,14 +1133,25 @@ void launch_w8_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd
             // static dealing over exactly the workgroups that are resident at once
             static OccCache occ;
             const int resident =
-                resident_per_cu(occ, reinterpret_cast<const void*>(&k_rows_w8<FULL, TRANS, BF>), 256, lds, true, 1);
-            hipLaunchKernelGGL((k_rows_w8<FULL, TRANS, BF>),
+                resident_per_cu(occ, reinterpret_cast<const void*>(&k_rows_w8<FULL, TRANS, BF, CF>), 256, lds, true, 1);
+            hipLaunchKernelGGL((k_rows_w8<FULL, TRANS, BF, CF>),
                                dim3(std::min<unsigned>((unsigned)(c->num_cu * resident), (s.nrows + 3) / 4)),
                                dim3(256), lds, st, args);
         }
         ProfScope ps(c, IALS_K_FALLBACK_USER + sd);
         launch_fallback_big(c, args);
     }
+}
+
+template <bool FULL, bool TRANS, bool BF>
+void launch_w8_nt(ials_ctx* c, const SweepArgs& args, const SideIndex& s, int sd) {
+    if constexpr (TRANS) {
+        if (!args.cur_full) {
+            launch_w8_nt_cf<FULL, TRANS, BF, false>(c, args, s, sd);
+            return;
+        }
+    }
+    launch_w8_nt_cf<FULL, TRANS, BF, true>(c, args, s, sd);
 }
 
 template <bool BF>
