@@ -862,7 +862,10 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
 // same 64 columns of G (and 4 x 64 different rows of X), so each 16 x 64 slice of G is loaded
 // once per block (one 16-byte load per thread) and read by every wavefront as 16-byte LDS reads
 // (stored column-major at a pitch of 20 floats: lane (q16, g4) of tile t reads the four
-// consecutive k-steps of column 16 t + q16).  Two slices alternate: the next one is loaded
+// consecutive k-steps of column 16 t + q16; the k-step index of column c is XORed with
+// 4 ((c / 16) mod 4), which keeps those reads free of bank conflicts and makes the staging
+// stores free of them too: without it the 64 lanes of a store met 4-way conflicts, 83 M
+// conflict cycles per launch on the MSD-shaped W).  Two slices alternate: the next one is loaded
 // while the current one is multiplied, one barrier per 16 columns of f.  Rows past n read row
 // 0 and are never written.
 // RT: row tiles of 16 per wavefront (4: 64 rows; 1 for tables with too few rows to give every
@@ -896,7 +899,7 @@ __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t
     };
     auto gstore = [&](int buf, floatx4 v) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) gs[buf][(4 * sq + c) * kGsPitch + sr] = v[c];
+        for (int c = 0; c < 4; ++c) gs[buf][(4 * sq + c) * kGsPitch + (sr ^ (4 * (sq >> 2)))] = v[c];
     };
     auto xload = [&](int fb, floatx4* a) {
         const int f = fb < d ? fb : 0;
@@ -906,7 +909,8 @@ __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t
     auto mma = [&](int buf, const floatx4* a) {
         floatx4 b[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) b[t] = *reinterpret_cast<const floatx4*>(&gs[buf][(16 * t + q16) * kGsPitch + 4 * g4]);
+        for (int t = 0; t < 4; ++t)
+            b[t] = *reinterpret_cast<const floatx4*>(&gs[buf][(16 * t + q16) * kGsPitch + 4 * (g4 ^ t)]);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
