@@ -863,9 +863,9 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
 // once per block (one 16-byte load per thread) and read by every wavefront as 16-byte LDS reads
 // (stored column-major at a pitch of 20 floats: lane (q16, g4) of tile t reads the four
 // consecutive k-steps of column 16 t + q16; the k-step index of column c is XORed with
-// 4 ((c / 16) mod 4), which keeps those reads free of bank conflicts and makes the staging
-// stores free of them too: without it the 64 lanes of a store met 4-way conflicts, 83 M
-// conflict cycles per launch on the MSD-shaped W).  Two slices alternate: the next one is loaded
+// 4 ((c / 16) mod 4), which spreads the 64 lanes of a staging store over all banks (without
+// it they met 4-way conflicts) and keeps the tile reads spread: 27 M instead of 83 M conflict
+// cycles per launch on the MSD-shaped W).  Two slices alternate: the next one is loaded
 // while the current one is multiplied, one barrier per 16 columns of f.  Rows past n read row
 // 0 and are never written.
 // RT: row tiles of 16 per wavefront (4: 64 rows; 1 for tables with too few rows to give every
