@@ -427,6 +427,16 @@ def rooflines(p, prec_name, kern, seg_len, epoch_s):
         "seg_item": _rate("seg_item", seg_bytes, 1e9, PEAK_HBM, "GB/s",
                           "item long-row segments, algorithmic gather bytes (partner block, id, slot, cache)"),
     }
+    if rates["seg_item"] is not None:
+        # the same launches against the matrix cores: 2b^2 + 4b FLOP per observation (Hessian
+        # as the full rank-1 update, gradient and prediction work), and the roofline that binds
+        seg_flops = seg_nnz * (2.0 * p.block * p.block + 4.0 * p.block)
+        seg_s = kern["seg_item"]["avg_ms"] / 1e3
+        mpeak = PEAK_MATRIX[prec_name]
+        rates["seg_item"].update({
+            "flop_achieved": round(seg_flops / seg_s / 1e12, 2), "flop_peak": mpeak, "flop_unit": "TFLOP/s",
+            "flop_frac": round(seg_flops / seg_s / 1e12 / mpeak, 4),
+            "bound": "mfma" if seg_flops / (mpeak * 1e12) > seg_bytes / (PEAK_HBM * 1e9) else "hbm"})
     floor_s, parts = epoch_floor(p, prec_name)
     eroof = {"floor_ms": round(floor_s * 1e3, 3), "epoch_ms": round(epoch_s * 1e3, 3),
              "frac": round(floor_s / epoch_s, 4),
