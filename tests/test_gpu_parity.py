@@ -209,6 +209,17 @@ def test_long_rows_split_into_segments():
     assert st["segments_item"] > 0 and st["long_rows_item"] > 0
 
 
+@pytest.mark.parametrize("seg_len", [1024, 2048])
+def test_other_segment_lengths(seg_len):
+    # the autotuner also picks segments of 1,024 or 2,048 observations; the longest item row
+    # (~2,400 observations) still spans more than one of them
+    p = synth.small_problem(61, 3000, 120, 60_000, 64, 64, labels=True, zipf_s=0.8, std=0.1)
+    lens = np.bincount(p.item, minlength=p.num_items)
+    assert lens.max() > seg_len
+    st = _epoch_check(p, 1, 1e-4, 1e-6, seg_len=seg_len)
+    assert st["segments_item"] > 0 and st["long_rows_item"] > 0
+
+
 @pytest.mark.parametrize("b", [32, 64])
 def test_long_rows_in_segment_groups(b):
     # segments of 256 observations: the longest item row (~2,400 observations) has 10
