@@ -171,6 +171,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 // its partial dot products (on top of base with inside), the later ones add theirs.  Slices
 // whose rows of H fit the Infinity Cache (256 MB) are re-read from it instead of HBM: the
 // observations of a user visit random items, each item row about |S| / |I| times per pass.
+__device__ inline float readlane_f(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
 template <int J, int UB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_predict_slice(
     int32_t U, int32_t d, int32_t f0, bool first, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
@@ -217,9 +220,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                     s = fmaf(w[j].z, h[v][j].z, s);
                     s = fmaf(w[j].w, h[v][j].w, s);
                 }
-#pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-                if (lane == t0 + v) mine = s;
+                // the 64-lane sum: each 16-lane row summed by DPP rotations, the four row
+                // sums read as scalars
+                s = row_sum16(s);
+                const float tot = (readlane_f(s, 0) + readlane_f(s, 16)) + (readlane_f(s, 32) + readlane_f(s, 48));
+                if (lane == t0 + v) mine = tot;
             }
         }
         if (lane < cnt) {
@@ -1140,9 +1145,10 @@ void launch_predict(ials_ctx* c, int32_t blk, bool inside, float* out) {
         hipLaunchKernelGGL((k_predict_wide<4, 4>), dim3(g), dim3(256), 0, c->stream, c->U, us.ptr, us.col, c->W, c->H,
                            p0, bw, inside, c->yhat, out);
     else if (c->d == 2048) {
-        // two slices of 1,024 columns: 168 MB of H per slice at the MSD shape
+        // two slices of 1,024 columns: 168 MB of H per slice at the MSD shape; eight
+        // observations' rows in flight per wavefront
         for (int f0 = 0; f0 < 2048; f0 += 1024)
-            hipLaunchKernelGGL((k_predict_slice<4, 4>), dim3(g), dim3(256), 0, c->stream, c->U, c->d, f0, f0 == 0,
+            hipLaunchKernelGGL((k_predict_slice<4, 8>), dim3(g), dim3(256), 0, c->stream, c->U, c->d, f0, f0 == 0,
                                us.ptr, us.col, c->W, c->H, p0, bw, inside, c->yhat, out);
     }
     else
