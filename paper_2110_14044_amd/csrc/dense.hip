@@ -113,6 +113,9 @@ __global__ __launch_bounds__(256) void k_predict_rows(int32_t U, const int64_t* 
 // The same for d = 256 J (J >= 2) with the whole wavefront on one observation: lane l
 // holds w_u[f] for f = 4 l + 256 j (j < J) and loads the same columns of h_i, UB observations
 // at a time with all their loads in flight, then each dot product is summed over the wave.
+__device__ inline float readlane_f(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
 template <int J, int UB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_predict_wide(int32_t U, const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ col, const float* __restrict__ W,
@@ -158,9 +161,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                     s = fmaf(w[j].z, h[v][j].z, s);
                     s = fmaf(w[j].w, h[v][j].w, s);
                 }
-#pragma unroll
-                for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-                if (lane == t0 + v) mine = s;
+                // the 64-lane sum: each 16-lane row summed by DPP rotations, the four row
+                // sums read as scalars
+                s = row_sum16(s);
+                const float tot = (readlane_f(s, 0) + readlane_f(s, 16)) + (readlane_f(s, 32) + readlane_f(s, 48));
+                if (lane == t0 + v) mine = tot;
             }
         }
         if (lane < cnt) out[c0 + lane] = inside ? base[c0 + lane] + mine : mine;
@@ -171,9 +176,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 // its partial dot products (on top of base with inside), the later ones add theirs.  Slices
 // whose rows of H fit the Infinity Cache (256 MB) are re-read from it instead of HBM: the
 // observations of a user visit random items, each item row about |S| / |I| times per pass.
-__device__ inline float readlane_f(float x, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
 template <int J, int UB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_predict_slice(
     int32_t U, int32_t d, int32_t f0, bool first, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
