@@ -875,8 +875,10 @@ __global__ __launch_bounds__(256) void k_dense_vec(int32_t n, int32_t d, int32_t
 // cycles per launch on the MSD-shaped W).  Two slices alternate: the next one is loaded
 // while the current one is multiplied, one barrier per 16 columns of f.  Rows past n read row
 // 0 and are never written.
-// RT: row tiles of 16 per wavefront (4: 64 rows; 1 for tables with too few rows to give every
-// CU a block at 256 rows per block, such as the item side at the MSD shape).
+// RT: row tiles of 16 per wavefront: 2 (32 rows, five wavefronts per SIMD; 64 rows at three
+// per SIMD was 12 % slower for the d = 1024 user table and the same at d = 2048), or 1 for
+// tables whose blocks of 256 rows would number fewer than two per CU, such as the item side
+// at the MSD shape.
 constexpr int kGsPitch = 20;
 template <int RT>
 __global__ __launch_bounds__(256) void k_dense_lds(int32_t n, int32_t d, int32_t B, const float* __restrict__ X,
@@ -1229,13 +1231,13 @@ void launch_gramian_slab(ials_ctx* c, const float* X, int32_t n, int32_t p0, int
 
 void launch_dense(ials_ctx* c, const float* X, int32_t n, int32_t p0, int32_t bw) {
     if (n == 0) return;
-    const unsigned grid = nblk(n, 256);  // 4 waves x 64 rows per block
+    const unsigned grid = nblk(n, 256);  // blocks of 4 waves x 64 rows
     const int B = c->B;
     if (B % 64 == 0 && c->d % 32 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(c->G) % 16 == 0) {
         if ((int64_t)grid * (B / 64) >= 2 * (int64_t)c->num_cu)
-            hipLaunchKernelGGL((k_dense_lds<4>), dim3(grid, (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d, B, X,
-                               c->G, p0, bw, c->alpha0, c->lambda, c->R0);
+            hipLaunchKernelGGL((k_dense_lds<2>), dim3(nblk(n, 128), (unsigned)(B / 64)), dim3(256), 0, c->stream, n,
+                               c->d, B, X, c->G, p0, bw, c->alpha0, c->lambda, c->R0);
         else
             hipLaunchKernelGGL((k_dense_lds<1>), dim3(nblk(n, 64), (unsigned)(B / 64)), dim3(256), 0, c->stream, n, c->d,
                                B, X, c->G, p0, bw, c->alpha0, c->lambda, c->R0);
