@@ -69,3 +69,30 @@ def test_epoch_work_matches_the_per_epoch_totals():
     floor16, parts16 = bench.epoch_floor(p, "bf16")
     assert parts16["hessian"] == pytest.approx(2 * (d // b) * S * (4 * b + 12) / 8e12, rel=1e-9)
     assert floor16 < floor
+
+
+def test_segment_rate_against_both_rooflines():
+    # 3,000 users x 120 items, 60k observations: most item rows are longer than 512, so the
+    # item segments carry most observations.  With a made-up launch time the segment entry
+    # must report the gather bytes against HBM and the 2b^2 + 4b FLOP per observation against
+    # the matrix peak, and name the matrix cores as the binding roofline at b = 64.
+    p = synth.small_problem(5, 3000, 120, 60_000, 128, 64, zipf_s=0.8)
+    li = np.bincount(p.item, minlength=p.num_items)
+    seg_nnz = int(li[li > 512].sum())
+    assert seg_nnz > 30_000
+    kern = {name: {"ms_per_epoch": 1.0, "launches": 2, "avg_ms": 0.5}
+            for name in ("rows_user", "rows_user_move", "rows_item", "seg_item", "gram_item", "dense_user",
+                         "predict")}
+    kern["rows_user_move"]["ms_per_epoch"] = 2.0
+    kern["seg_item"]["avg_ms"] = 0.002  # large rates, so the rounding to 0.01 does not matter
+    roof, rates, eroof = bench.rooflines(p, "fp32", kern, 512, 0.01)
+    s = rates["seg_item"]
+    t = 0.002e-3
+    assert s["achieved"] == pytest.approx(seg_nnz * (4 * 64 + 12) / t / 1e9, rel=1e-3)
+    assert s["flop_achieved"] == pytest.approx(seg_nnz * (2 * 64 * 64 + 4 * 64) / t / 1e12, rel=1e-3)
+    assert s["flop_frac"] == pytest.approx(s["flop_achieved"] / 157.3, rel=1e-3)
+    assert s["bound"] == "mfma"
+    # at b = 4 the same observations gather 28 bytes for 48 FLOP: HBM binds
+    p4 = synth.small_problem(5, 3000, 120, 60_000, 16, 4, zipf_s=0.8)
+    _, rates4, _ = bench.rooflines(p4, "fp32", kern, 512, 0.01)
+    assert rates4["seg_item"]["bound"] == "hbm"
